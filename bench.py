@@ -1,0 +1,318 @@
+#!/usr/bin/env python3
+"""Benchmark of the direct-sum N-body hot path on one MI355X.
+
+Default workload: the 10,425-body Solar-System system (Sun, 30 major bodies,
+100 minor moons, 19 heavy and 10,275 small asteroids; seed 1), dt = 0.1 day.
+A step is one velocity-Verlet step (one all-pairs force pass plus the fused
+kick-drift-kick epilogue).  The line reports pair interactions/s and steps/s
+for the FP64 form (the headline `value`) and for the split-precision form,
+with both forms' energy errors, the force kernel's roofline fraction and the
+CPU oracle's rate on this host.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py --workload {solar-131,solar-131072,ensemble,adjoint}
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pair interactions/s + steps/s at N=10,425: FP64 vs split-precision at fixed ΔE/E"
+FP64_PEAK_TFLOPS = 78.6          # MI355X vector FP64, 256 CU x 64 lanes x 2 x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+FLOPS_PER_PAIR = 20              # algorithmic convention for one pair interaction
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="solar-10425",
+                    choices=["solar-10425", "solar-131", "solar-131072", "ensemble", "adjoint"])
+    ap.add_argument("--no-tune", action="store_true", help="use the heuristic tile shapes")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="approximate CPU time budget of the oracle sample")
+    ap.add_argument("--fd-coords", type=int, default=64, help="adjoint workload: FD coordinates")
+    return ap.parse_args()
+
+
+def read_traffic(kernel_key):
+    """HBM traffic per launch from a committed rocprofv3 --pmc summary, if one
+    exists for this kernel (lines 'key: value' in profiles/<kernel_key>.txt)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_key}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.lstrip().startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the force pass would "
+              "shard by targets with a per-step all-gather of positions; see DESIGN.md). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import solar_ics as S
+    import paper_2112_15079_amd as nb
+
+    if not torch.cuda.is_available():
+        print("no GPU visible: the benchmark needs an MI355X", file=sys.stderr)
+        sys.exit(3)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    if args.workload == "ensemble":
+        return bench_ensemble(args, S, nb, torch, np, dev)
+    if args.workload == "adjoint":
+        return bench_adjoint(args, S, nb, torch, np, dev)
+    k = {"solar-131": 0, "solar-10425": 1, "solar-131072": 2}[args.workload]
+    return bench_single(args, k, S, nb, torch, np, dev)
+
+
+def _t(a, torch, dev):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+def bench_single(args, k, S, nb, torch, np_, dev):
+    s = S.config(k)
+    n, G, dt = s.n, s.G, s.dt
+    K = args.steps if args.steps is not None else {0: 3650, 1: 10000, 2: 200}[k]
+    W = args.warmup if args.warmup is not None else {0: 365, 1: 200, 2: 10}[k]
+    log(f"workload {s.name}: n={n}, dt={dt}, steps={K}, warmup={W}")
+    pos0, vel0, m = _t(s.pos, torch, dev), _t(s.vel, torch, dev), _t(s.mass, torch, dev)
+
+    tiles = {}
+    for prec in ("fp64", "split"):
+        if not args.no_tune:
+            tile, ms = nb.autotune(pos0, m, G, prec)
+            log(f"autotune {prec}: {tile} {ms:.4f} ms per force pass")
+        tiles[prec] = nb.get_tile(0, prec, n)
+
+    E0 = nb.energy(pos0, vel0, m, G)[2].item()
+    results = {}
+    for prec in ("fp64", "split"):
+        p, v = pos0.clone(), vel0.clone()
+        nb.verlet_run(p, v, m, G, dt, W, precision=prec)        # warm-up (graphs, caches)
+        torch.cuda.synchronize()
+        p, v = pos0.clone(), vel0.clone()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record()
+        nb.verlet_run(p, v, m, G, dt, K, precision=prec)
+        ev1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gpu_s = ev0.elapsed_time(ev1) / 1e3
+        E1 = nb.energy(p, v, m, G)[2].item()
+        results[prec] = dict(wall=wall, gpu=gpu_s, E=E1, pos=p, vel=v)
+        log(f"{prec}: {K} steps in {wall:.4f} s wall ({gpu_s:.4f} s events), "
+            f"dE/E = {(E1 - E0) / abs(E0):.3e}")
+
+    pairs = n * (n - 1)
+    r64, rsp = results["fp64"], results["split"]
+
+    def rate(r):
+        return (K + 1) * pairs / r["wall"], K / r["wall"]
+
+    v64, sps64 = rate(r64)
+    vsp, spssp = rate(rsp)
+
+    # per-step acceleration error against the CPU oracle at the initial state
+    import oracle
+    if n <= 20000:
+        a_ref = oracle.accel(s.pos, s.mass, G)
+        idx = None
+    else:
+        rng = np.random.default_rng(0)
+        idx = np.unique(np.concatenate([[0, n - 1], rng.choice(n, 254, replace=False)]))
+        a_ref = oracle.accel_targets(s.pos, s.mass, G, idx)
+
+    def acc_err(prec):
+        a = nb.accel(pos0, m, G, precision=prec).cpu().numpy()
+        if idx is not None:
+            a = a[:, idx]
+        return float(np.max(np.linalg.norm(a - a_ref, axis=0) / np.linalg.norm(a_ref, axis=0)))
+
+    err64, errsp = acc_err("fp64"), acc_err("split")
+
+    # force-kernel timing for the roofline (HIP events around the force kernels only)
+    reps = max(20, min(2000, int(2e11 / pairs)))
+    ms64 = nb.time_force(pos0, m, G, "fp64", reps=reps)
+    mssp = nb.time_force(pos0, m, G, "split", reps=reps)
+    flops = FLOPS_PER_PAIR * pairs
+    achieved = flops / (ms64 * 1e-3) / 1e12
+    roof = {"bound": "alu", "kernel": "k_force<fp64>", "achieved": round(achieved, 3),
+            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+            "traffic": read_traffic(f"force_fp64_n{n}"),
+            "ms_per_launch": round(ms64, 5), "flops_per_launch": flops,
+            "split_ms_per_launch": round(mssp, 5)}
+    log(f"force pass: fp64 {ms64:.4f} ms ({achieved:.2f} TFLOP/s alg.), split {mssp:.4f} ms")
+
+    line = {
+        "metric": METRIC,
+        "value": v64,
+        "unit": "pair interactions/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * r64["wall"] / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{s.name}: Sun, {s.counts.get('major', 0)} major, "
+                               f"{s.counts.get('moons', 0)} moons, {s.counts.get('heavy', 0)} heavy, "
+                               f"{s.counts.get('small', 0)} small asteroids; seed {k if k < 3 else ''}",
+                   "n": n, "dt_days": dt, "steps": K, "tile": tiles["fp64"]},
+        "steps_per_s": sps64,
+        "fp64": {"pairs_per_s": v64, "steps_per_s": sps64, "dE_over_E": (r64["E"] - E0) / abs(E0),
+                 "accel_max_rel_err_vs_oracle": err64, "gpu_event_s": r64["gpu"]},
+        "split": {"pairs_per_s": vsp, "steps_per_s": spssp, "ms_per_step": 1e3 * rsp["wall"] / K,
+                  "dE_over_E": (rsp["E"] - E0) / abs(E0),
+                  "E_split_minus_E_fp64_over_E0": (rsp["E"] - r64["E"]) / abs(E0),
+                  "accel_max_rel_err_vs_oracle": errsp, "speedup_vs_fp64": vsp / v64,
+                  "tile": tiles["split"], "gpu_event_s": rsp["gpu"]},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds, k)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(s, budget_s, k):
+    """The oracle (plain FP64 C, OpenMP over targets) on this host's cores, on
+    a bounded prefix of the same run."""
+    import oracle
+    n = s.n
+    t1, _, _ = oracle.timed_verlet(s.pos, s.vel, s.mass, s.G, s.dt, 1)   # 2 force passes
+    per_pass = t1 / 2
+    steps = int(max(1, min(2000, budget_s / max(per_pass, 1e-9) - 1)))
+    log(f"cpu baseline: oracle on {oracle.get_threads()} threads, {steps} steps")
+    t, _, _ = oracle.timed_verlet(s.pos, s.vel, s.mass, s.G, s.dt, steps)
+    pairs = (steps + 1) * n * (n - 1)
+    return {"value": pairs / t, "unit": "pair interactions/s", "cores": oracle.get_threads(),
+            "kind": "oracle", "steps_per_s": steps / t,
+            "sample": f"first {steps} steps of the same {n}-body run ({steps + 1} force passes, "
+                      f"{t:.1f} s)",
+            "host_cpus": os.cpu_count()}
+
+
+def bench_ensemble(args, S, nb, torch, np, dev):
+    K = args.steps if args.steps is not None else 1000
+    W = args.warmup if args.warmup is not None else 5
+    log("building the 512-system ensemble")
+    systems, offs = S.ensemble(512)
+    cat = lambda f: np.ascontiguousarray(np.concatenate([f(x) for x in systems], axis=-1))
+    pos0, vel0, m = (_t(cat(lambda x: x.pos), torch, dev), _t(cat(lambda x: x.vel), torch, dev),
+                     _t(cat(lambda x: x.mass), torch, dev))
+    G, dt = S.G_AU_DAY_MSUN, 0.1
+    pairs = int(sum(x.n * (x.n - 1) for x in systems))
+    out = {"metric": "ensemble pair interactions/s", "unit": "pair interactions/s", "steps": K,
+           "warmup": W, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "512 systems: Sun, 30 majors, U{100..8192} asteroids, seeds 100..611",
+                      "bodies": int(offs[-1]), "pairs_per_step": pairs}}
+    for prec in ("fp64", "split"):
+        p, v = pos0.clone(), vel0.clone()
+        nb.verlet_run_batched(p, v, m, offs, G, dt, W, precision=prec)
+        torch.cuda.synchronize()
+        p, v = pos0.clone(), vel0.clone()
+        t0 = time.perf_counter()
+        nb.verlet_run_batched(p, v, m, offs, G, dt, K, precision=prec)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[prec] = {"pairs_per_s": (K + 1) * pairs / wall, "steps_per_s": K / wall, "wall_s": wall}
+        log(f"ensemble {prec}: {wall:.3f} s, {(K + 1) * pairs / wall:.3e} pairs/s")
+    out["value"] = out["fp64"]["pairs_per_s"]
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(args, S, nb, torch, np, dev):
+    s = S.config(4)
+    K = args.steps if args.steps is not None else s.steps
+    n, G, dt = s.n, s.G, s.dt
+    first = 1 + s.counts["major"]
+    m = _t(s.mass, torch, dev)
+    pt, vt = _t(S.adjoint_target_perturbation(s), torch, dev), _t(s.vel, torch, dev)
+    nb.verlet_run(pt, vt, m, G, dt, K)
+    tgt = pt.cpu().numpy()
+
+    def final(p0, v0, m0):
+        p, v = _t(p0, torch, dev), _t(v0, torch, dev)
+        nb.verlet_run(p, v, _t(m0, torch, dev), G, dt, K)
+        return p.cpu().numpy()
+
+    pT = final(s.pos, s.vel, s.mass)
+    lam = np.zeros_like(pT)
+    lam[:, first:] = 2 * (pT[:, first:] - tgt[:, first:])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gr, gv, gm, _, _ = nb.verlet_adjoint(_t(s.pos, torch, dev), _t(s.vel, torch, dev), m, G, dt, K,
+                                         100, _t(lam, torch, dev), _t(np.zeros_like(lam), torch, dev))
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    log(f"adjoint of {K} steps: {t_adj:.2f} s")
+    grad = np.concatenate([gr.cpu().numpy().ravel(), gv.cpu().numpy().ravel(),
+                           gm.cpu().numpy()[1:31]])
+    coords = S.fd_coordinates(s, args.fd_coords)
+    rows = []
+    for idx in coords:
+        p0, v0, m0 = s.pos.copy(), s.vel.copy(), s.mass.copy()
+        if idx < 3 * n:
+            arr, flat, h = p0, idx, 1e-7 * max(abs(p0.ravel()[idx]), 1.0)
+        elif idx < 6 * n:
+            arr, flat = v0, idx - 3 * n
+            h = 1e-7 * max(abs(v0.ravel()[flat]), 0.01)
+        else:
+            arr, flat = m0, 1 + idx - 6 * n
+            h = 1e-7 * m0[flat]
+        base = arr.ravel()[flat]
+        arr.ravel()[flat] = base + h
+        pp = final(p0, v0, m0)
+        arr.ravel()[flat] = base - h
+        pm = final(p0, v0, m0)
+        a, b = pp[:, first:] - tgt[:, first:], pm[:, first:] - tgt[:, first:]
+        fd = float(np.sum((pp[:, first:] - pm[:, first:]) * (a + b)) / (2 * h))
+        rows.append((int(idx), float(grad[idx]), fd))
+        log(f"coord {idx}: adjoint {grad[idx]: .9e} fd {fd: .9e}")
+    fds = np.array([r[2] for r in rows])
+    adj = np.array([r[1] for r in rows])
+    scale = np.abs(fds).max()
+    relerr = np.abs(adj - fds) / np.maximum(np.abs(fds), 1e-300)
+    ok = (relerr <= 1e-6) | (np.abs(adj - fds) <= 1e-9 * scale)
+    print(json.dumps({"metric": "adjoint vs central finite differences", "steps": K, "n": n,
+                      "adjoint_s": t_adj, "coords": len(rows), "pass": int(ok.sum()),
+                      "max_rel_err": float(relerr.max()),
+                      "median_rel_err": float(np.median(relerr)), "rows": rows}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

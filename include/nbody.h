@@ -1,0 +1,195 @@
+/*
+ * nbody.h - C ABI of the MI355X (gfx950) direct-sum N-body library.
+ *
+ * The method (Zhu, "N-body Simulations of the Solar System with CPU-based
+ * Parallel Methods"):
+ *   Eq. (1)       a_p = sum_{j != p} G m_j (r_j - r_p) / |r_j - r_p|^3
+ *   Eqs. (3)-(4)  velocity Verlet: r_{i+1} = r_i + v_i dt + a_i dt^2 / 2,
+ *                 v_{i+1} = v_i + (a_i + a_{i+1}) dt / 2.
+ *
+ * Conventions shared by every entry point
+ *   - Array pointers are DEVICE pointers (hipMalloc'd or torch CUDA tensors)
+ *     unless the name ends in _host.  All floating point is IEEE double.
+ *   - Layout is structure of arrays with plane stride n:
+ *       pos[0..n) = x, pos[n..2n) = y, pos[2n..3n) = z   (same for vel, acc,
+ *       gradients); mass[0..n).
+ *   - Units are the caller's; G must be in those units.  No softening: the
+ *     self pair j = p is excluded by index, and two distinct bodies at the
+ *     same point give non-finite values, as Eq. (1) does.  Squared
+ *     separations must lie inside the FP32 normal range (1e-37 .. 1e37 in
+ *     the caller's units), because the reciprocal square root is seeded in
+ *     FP32 and refined in FP64.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued asynchronously on it; results are ready when the stream is.
+ *   - Ownership: the caller owns every buffer.  Scratch memory is the
+ *     caller's `workspace` of at least nbody_workspace_bytes(...) bytes
+ *     (256-byte aligned); the library allocates no device memory.  It keeps
+ *     only its tile-shape table and captured step graphs, both released by
+ *     nbody_reset_caches().
+ *   - Errors: arguments are validated before anything is enqueued; a bad
+ *     argument returns NBODY_EINVAL (nothing enqueued), a short workspace
+ *     NBODY_EWORKSPACE, a HIP failure NBODY_EHIP.  nbody_last_error() gives
+ *     a message for the calling thread.  Device faults surface at the
+ *     caller's next synchronisation.  No C++ exception crosses this ABI.
+ *   - Calls that share a workspace must not overlap in time.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NBODY_OK = 0,
+    NBODY_EINVAL = 1,        /* bad argument; nothing enqueued */
+    NBODY_EUNSUPPORTED = 2,  /* valid but not supported (e.g. n too large) */
+    NBODY_EWORKSPACE = 3,    /* workspace NULL or smaller than required */
+    NBODY_EHIP = 4           /* a HIP runtime call failed */
+} nbody_status;
+
+typedef enum {
+    /* FP64 throughout; r^-3 to full FP64 accuracy. */
+    NBODY_FP64 = 0,
+    /* Split precision: FP64 displacement, kicks, drifts and accumulation of
+     * sources with mass >= small_mass; 1/|r|^3 from an FP32 reciprocal
+     * square root refined by one FP64 Newton step for those sources;
+     * sources lighter than small_mass are summed in FP32 with Kahan
+     * compensation. */
+    NBODY_SPLIT = 1
+} nbody_precision;
+
+typedef enum {
+    NBODY_OP_ACCEL = 0,
+    NBODY_OP_RUN = 1,
+    NBODY_OP_ADJOINT = 2,
+    NBODY_OP_BATCHED = 3,
+    NBODY_OP_ENERGY = 4
+} nbody_op;
+
+/* Bytes of workspace that `op` needs.  n_total: bodies (for BATCHED, the sum
+ * over systems); num_systems: systems (1 unless BATCHED); steps and
+ * checkpoint_every: only used by ADJOINT.  Returns 0 for invalid input. */
+size_t nbody_workspace_bytes(int32_t op, int64_t n_total, int32_t num_systems,
+                             int64_t steps, int64_t checkpoint_every,
+                             int32_t precision);
+
+/* Eq. (1): acc_out[3n] = accelerations of all n bodies at positions pos.
+ * vel, dt and steps are accepted for a uniform argument block and ignored
+ * (vel may be NULL).  precision: nbody_precision; small_mass is the split
+ * threshold in mass units (ignored for NBODY_FP64).  n >= 1. */
+int32_t nbody_accel(const double* pos, const double* vel, const double* mass,
+                    int64_t n, double G, double dt, int64_t steps,
+                    double* acc_out, int32_t precision, double small_mass,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* Eqs. (3)-(4): advance (pos, vel) in place by `steps` velocity-Verlet steps
+ * of size dt.  a(r_0) is computed first, then one evaluation of Eq. (1) per
+ * step, so a run of n steps followed by one of m steps equals one run of
+ * n + m steps bit for bit.  steps = 0 is a no-op.  The step sequence is the
+ * kick-drift-kick form, which is Eqs. (3)-(4) rearranged (a_{i+1} is reused
+ * as the next step's a_i).  Sets the non-finite flag read by
+ * nbody_get_flags when any r, v or a stops being finite. */
+int32_t nbody_verlet_run(double* pos, double* vel, const double* mass,
+                         int64_t n, double G, double dt, int64_t steps,
+                         int32_t precision, double small_mass,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
+/* Gradient of a scalar loss L(r_T, v_T) of the FP64 run of Eqs. (3)-(4)
+ * started from (pos0, vel0) with masses `mass`: the exact discrete adjoint
+ * of the step map (reverse sweep, one Jacobian-transpose product of Eq. (1)
+ * per step).  Inputs grad_posT = dL/dr_T, grad_velT = dL/dv_T ([3n] each).
+ * Outputs grad_pos0, grad_vel0 ([3n]) and grad_mass ([n]); pos_out/vel_out
+ * ([3n], may be NULL) receive r_T, v_T.  The forward run is stored every
+ * checkpoint_every steps and recomputed segment by segment during the
+ * reverse sweep.  Inputs are not modified.  checkpoint_every >= 1. */
+int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const double* mass,
+                             int64_t n, double G, double dt, int64_t steps,
+                             int64_t checkpoint_every,
+                             const double* grad_posT, const double* grad_velT,
+                             double* grad_pos0, double* grad_vel0, double* grad_mass,
+                             double* pos_out, double* vel_out,
+                             void* workspace, size_t workspace_bytes, void* stream);
+
+/* Eqs. (3)-(4) for num_systems independent systems in one launch per step.
+ * System k owns bodies [offsets_host[k], offsets_host[k+1]) of the
+ * concatenated SoA arrays (plane stride = offsets_host[num_systems]); bodies
+ * of different systems do not interact.  offsets_host is a HOST array of
+ * num_systems + 1 non-decreasing values starting at 0; every system has at
+ * least one body.  The step loop is captured into a HIP graph on first use
+ * and replayed. */
+int32_t nbody_verlet_run_batched(double* pos, double* vel, const double* mass,
+                                 const int64_t* offsets_host, int32_t num_systems,
+                                 double G, double dt, int64_t steps,
+                                 int32_t precision, double small_mass,
+                                 void* workspace, size_t workspace_bytes, void* stream);
+
+/* Sec. 2 accuracy measure: out[0] = kinetic sum m|v|^2/2, out[1] = potential
+ * -sum_{i<j} G m_i m_j / |r_i - r_j|, out[2] = total.  `out` is a DEVICE
+ * array of 3 doubles.  FP64 with compensated sums; deterministic. */
+int32_t nbody_energy(const double* pos, const double* vel, const double* mass,
+                     int64_t n, double G, double* out,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* Total linear and angular momentum: out[0..3) = sum m v,
+ * out[3..6) = sum m r x v (DEVICE array of 6 doubles, compensated). */
+int32_t nbody_momenta(const double* pos, const double* vel, const double* mass,
+                      int64_t n, double* out, void* stream);
+
+/* Flags set by the last runs on this workspace (bit 0: a non-finite r, v or
+ * a was produced).  Synchronises `stream`.  clear != 0 resets them. */
+int32_t nbody_get_flags(void* workspace, void* stream, int32_t clear, int32_t* flags_host);
+
+/* Tile shape of the force pass: targets per lane (1, 2, 4), waves per
+ * workgroup (1, 2, 4, 8) and source chunks (1..64). */
+typedef struct {
+    int32_t targets_per_lane;
+    int32_t waves;
+    int32_t chunks;
+} nbody_tile;
+
+/* The tile shape the library will use for (kind, precision, n): the tuned
+ * one if nbody_autotune ran for that size class, else a heuristic.
+ * kind: 0 = force pass, 1 = adjoint pass. */
+int32_t nbody_get_tile(int32_t kind, int32_t precision, int64_t n, nbody_tile* tile_host);
+
+/* Force a tile shape for (kind, precision, n's size class); shapes outside
+ * the supported set return NBODY_EINVAL. */
+int32_t nbody_set_tile(int32_t kind, int32_t precision, int64_t n, const nbody_tile* tile_host);
+
+/* Time candidate tile shapes for (kind, precision) on the caller's data with
+ * HIP events and keep the fastest for n's size class.  pos and mass as for
+ * nbody_accel; synchronises `stream`.  best_host (may be NULL) receives the
+ * winner and best_ms_host (may be NULL) its time per force pass. */
+int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const double* mass,
+                       int64_t n, double G, double small_mass,
+                       void* workspace, size_t workspace_bytes, void* stream,
+                       nbody_tile* best_host, double* best_ms_host);
+
+/* Average duration (ms) of one force pass (kind 0: Eq. (1) for `precision`;
+ * kind 1: the adjoint's transpose-Jacobian pass) over `reps` back-to-back
+ * launches with the current tile shape, timed by HIP events recorded on
+ * `stream` around the force kernels only.  Inputs as for nbody_accel (kind 1
+ * uses a constant cotangent).  Synchronises `stream`. */
+int32_t nbody_time_force(int32_t kind, int32_t precision, const double* pos, const double* mass,
+                         int64_t n, double G, double small_mass, int32_t reps,
+                         void* workspace, size_t workspace_bytes, void* stream,
+                         double* ms_per_pass_host);
+
+/* Drops captured graphs and tuned tile shapes. */
+void nbody_reset_caches(void);
+
+/* Message describing the calling thread's last failure ("" if none). */
+const char* nbody_last_error(void);
+
+/* Library version string. */
+const char* nbody_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBODY_H */

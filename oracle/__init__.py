@@ -61,6 +61,7 @@ def _load():
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_get_threads.restype = ctypes.c_int
     lib.oracle_accel.argtypes = [_I64, _D, _P, _P, _P]
+    lib.oracle_accel_targets.argtypes = [_I64, _D, _P, _P, _P, _I64, _P]
     lib.oracle_verlet.argtypes = [_I64, _D, _D, _I64, _P, _P, _P, _P]
     lib.oracle_verlet.restype = ctypes.c_int
     lib.oracle_euler.argtypes = [_I64, _D, _D, _I64, _P, _P, _P]
@@ -104,6 +105,20 @@ def accel(pos, mass, G):
     acc = np.empty((3, n))
     lib.oracle_accel(n, G, _ptr(pos), _ptr(mass), _ptr(acc))
     return acc
+
+
+def accel_targets(pos, mass, G, idx):
+    """Eq. (1) for the targets ``idx`` only; returns (3, len(idx))."""
+    lib = _load()
+    mass = _c(mass)
+    n = mass.shape[0]
+    pos = _c(pos, (3, n))
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    if idx.size and (idx.min() < 0 or idx.max() >= n):
+        raise IndexError("target index out of range")
+    out = np.empty((idx.size, 3))
+    lib.oracle_accel_targets(n, G, _ptr(pos), _ptr(mass), _ptr(idx), idx.size, _ptr(out))
+    return np.ascontiguousarray(out.T)
 
 
 def verlet(pos, vel, mass, G, dt, steps, trajectory=False):

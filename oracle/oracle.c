@@ -106,6 +106,37 @@ void oracle_accel(int64_t n, double G, const double* pos, const double* mass, do
     }
 }
 
+/* Eq. (1) for the listed targets only: acc[3*k + c] for target idx[k],
+ * component c (same loop as oracle_accel, for sampled checks at large n). */
+void oracle_accel_targets(int64_t n, double G, const double* pos, const double* mass,
+                          const int64_t* idx, int64_t count, double* acc)
+{
+    const double* x = pos;
+    const double* y = pos + n;
+    const double* z = pos + 2 * n;
+    int64_t k;
+#pragma omp parallel for schedule(static)
+    for (k = 0; k < count; ++k) {
+        int64_t p = idx[k];
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == p) continue;
+            double dx = x[j] - x[p];
+            double dy = y[j] - y[p];
+            double dz = z[j] - z[p];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            double r = sqrt(r2);
+            double s = G * mass[j] / (r2 * r);
+            ax += s * dx;
+            ay += s * dy;
+            az += s * dz;
+        }
+        acc[3 * k] = ax;
+        acc[3 * k + 1] = ay;
+        acc[3 * k + 2] = az;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Eqs. (3)-(4)                                                               */
 /* ------------------------------------------------------------------------ */

@@ -1,0 +1,20 @@
+"""Direct-sum Solar-System N-body on AMD Instinct MI355X (gfx950).
+
+Eq. (1) of Zhu, "N-body Simulations of the Solar System with CPU-based
+Parallel Methods", evaluated every step inside the velocity-Verlet integrator
+of Eqs. (3)-(4), as hand-written HIP kernels behind the C ABI of
+``include/nbody.h``; this package is its Python binding.
+
+    from paper_2112_15079_amd import accel, verlet_run, verlet_adjoint, \
+        verlet_run_batched, energy, momenta, VerletRun
+"""
+from .nbody import (SMALL_MASS_MSUN, accel, autotune, energy, get_flags, get_tile, momenta,
+                    reset_caches, set_tile, time_force, verlet_adjoint, verlet_run, verlet_run_batched,
+                    version)
+from .autograd import VerletRun, verlet
+
+__all__ = [
+    "accel", "verlet_run", "verlet_adjoint", "verlet_run_batched", "energy", "momenta",
+    "get_flags", "get_tile", "set_tile", "autotune", "time_force", "reset_caches", "version", "VerletRun",
+    "verlet", "SMALL_MASS_MSUN",
+]

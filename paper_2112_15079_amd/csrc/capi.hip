@@ -1,0 +1,1010 @@
+// C ABI of the library (declared in include/nbody.h): argument validation,
+// workspace layout, the step loop of Eqs. (3)-(4) with HIP-graph replay, the
+// reverse sweep of the discrete adjoint, the batched ensemble and the tile
+// autotuner.  Every floating-point step runs in the kernels; this file only
+// sequences launches.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "common.hpp"
+#include "nbody.h"
+
+using namespace nb;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// errors
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define NB_HIP(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(NBODY_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+#define NB_TRY(expr)                       \
+    do {                                   \
+        int s_ = (expr);                   \
+        if (s_ != NBODY_OK) return s_;     \
+    } while (0)
+
+constexpr int64_t kMaxBodies = (int64_t)1 << 30;
+
+// ---------------------------------------------------------------------------
+// tile table
+
+std::mutex g_mu;
+std::map<std::tuple<int, int, int>, Tile> g_tiles;   // (kind, precision, size class)
+
+constexpr int kBatchChunkMax = 16;
+
+int size_class(int64_t n)
+{
+    // quarter-octave classes
+    return (int)std::floor(4.0 * std::log2((double)std::max<int64_t>(n, 1)));
+}
+
+// Chunks allowed by the workspace: part buffers hold at most this many.
+int chunk_cap(int64_t n)
+{
+    const int64_t c = ((int64_t)1 << 22) / std::max<int64_t>(n, 1);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxChunks, c));
+}
+
+Tile heuristic_tile(int kind, int64_t n)
+{
+    if (kind == 2) return Tile{2, 1, kBatchChunkMax};   // ensemble: per-system chunks
+    Tile t;
+    t.tpl = kind == 0 ? 2 : 1;
+    t.waves = 1;
+    const int64_t tb = (n + 64 * t.waves * t.tpl - 1) / (64 * t.waves * t.tpl);
+    int64_t c = std::max<int64_t>(1, 2048 / tb);
+    c = std::min<int64_t>(c, std::max<int64_t>(1, n / 256));
+    t.chunks = (int)std::min<int64_t>(c, chunk_cap(n));
+    return t;
+}
+
+Tile pick_tile(int kind, int prec, int64_t n)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_tiles.find(std::make_tuple(kind, prec, size_class(n)));
+        if (it != g_tiles.end()) {
+            Tile t = it->second;
+            t.chunks = std::min(t.chunks, chunk_cap(n));
+            return t;
+        }
+    }
+    return heuristic_tile(kind, n);
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+
+struct Layout {
+    size_t flags = 0, part = 0, alt = 0, perm = 0, nmaj = 0, offs = 0, pos_c = 0, vel_c = 0,
+           mass_c = 0, alt_c = 0, rows = 0, units = 0, bchunks = 0, ck = 0, seg = 0, lam_r = 0,
+           lam_v = 0, g_m = 0, u = 0, vtmp = 0, total = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Alloc {
+    size_t off = 0;
+    size_t take(size_t bytes)
+    {
+        const size_t o = off;
+        off = align256(off + std::max<size_t>(bytes, 1));
+        return o;
+    }
+};
+
+Layout layout(int op, int64_t n, int32_t ns, int64_t steps, int64_t K, int prec)
+{
+    Layout L;
+    Alloc a;
+    const size_t d = sizeof(double);
+    L.flags = a.take(256);
+    const int cap = (op == NBODY_OP_BATCHED) ? kBatchChunkMax : chunk_cap(n);
+    const int planes = (op == NBODY_OP_ADJOINT) ? 4 : 3;
+    L.part = a.take((size_t)cap * planes * n * d);
+    L.alt = a.take(3 * n * d);
+    if (prec == NBODY_SPLIT && op != NBODY_OP_ADJOINT && op != NBODY_OP_ENERGY) {
+        L.perm = a.take(n * sizeof(int32_t));
+        L.nmaj = a.take((size_t)ns * sizeof(int64_t));
+        L.offs = a.take((size_t)(ns + 1) * sizeof(int64_t));
+        L.pos_c = a.take(3 * n * d);
+        L.vel_c = a.take(3 * n * d);
+        L.mass_c = a.take(n * d);
+        L.alt_c = a.take(3 * n * d);
+    }
+    if (op == NBODY_OP_ENERGY) L.rows = a.take(n * d);
+    if (op == NBODY_OP_BATCHED) {
+        if (!L.offs) L.offs = a.take((size_t)(ns + 1) * sizeof(int64_t));
+        // units: per system ceil(n_k/64) target blocks (the smallest tile) times
+        // at most kBatchChunkMax chunks.
+        const int64_t max_units = (n / 64 + ns) * kBatchChunkMax;
+        L.units = a.take((size_t)max_units * sizeof(BatchUnit));
+        L.bchunks = a.take(n);
+    }
+    if (op == NBODY_OP_ADJOINT) {
+        const int64_t nck = (steps + K - 1) / K;
+        L.ck = a.take((size_t)(nck + 1) * 6 * n * d);
+        L.seg = a.take((size_t)std::min(K, std::max<int64_t>(steps, 1)) * 3 * n * d);
+        L.lam_r = a.take(3 * n * d);
+        L.lam_v = a.take(3 * n * d);
+        L.g_m = a.take(n * d);
+        L.u = a.take(3 * n * d);
+        L.vtmp = a.take(3 * n * d);
+    }
+    L.total = a.off;
+    return L;
+}
+
+template <typename T>
+T* at(void* ws, size_t off)
+{
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// ---------------------------------------------------------------------------
+// validation
+
+int check_common(const void* pos, const void* mass, int64_t n, double G)
+{
+    if (!pos || !mass) return fail(NBODY_EINVAL, "null position or mass pointer");
+    if (n < 1) return fail(NBODY_EINVAL, "n must be >= 1 (got %lld)", (long long)n);
+    if (n > kMaxBodies) return fail(NBODY_EUNSUPPORTED, "n = %lld exceeds 2^30", (long long)n);
+    if (!std::isfinite(G)) return fail(NBODY_EINVAL, "G is not finite");
+    return NBODY_OK;
+}
+
+int check_prec(int32_t prec, double small_mass)
+{
+    if (prec != NBODY_FP64 && prec != NBODY_SPLIT)
+        return fail(NBODY_EINVAL, "unknown precision %d", prec);
+    if (prec == NBODY_SPLIT && !(small_mass >= 0.0 && std::isfinite(small_mass)))
+        return fail(NBODY_EINVAL, "split threshold must be finite and >= 0");
+    return NBODY_OK;
+}
+
+int check_ws(const void* ws, size_t have, size_t need)
+{
+    if (!ws) return fail(NBODY_EWORKSPACE, "workspace is NULL (need %zu bytes)", need);
+    if (have < need) return fail(NBODY_EWORKSPACE, "workspace has %zu bytes, need %zu", have, need);
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+        return fail(NBODY_EINVAL, "workspace must be 256-byte aligned");
+    return NBODY_OK;
+}
+
+// ---------------------------------------------------------------------------
+// graph capture: a private capture stream per device (default priority).
+
+std::map<int, hipStream_t> g_capture_streams;
+
+int capture_stream(hipStream_t* out)
+{
+    int dev = 0;
+    NB_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_capture_streams.find(dev);
+    if (it == g_capture_streams.end()) {
+        hipStream_t s = nullptr;
+        NB_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        it = g_capture_streams.emplace(dev, s).first;
+    }
+    *out = it->second;
+    return NBODY_OK;
+}
+
+struct GraphKey {
+    std::vector<uint64_t> v;
+    bool operator<(const GraphKey& o) const { return v < o.v; }
+};
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+std::map<GraphKey, GraphEntry> g_graphs;
+
+void drop_graphs()
+{
+    for (auto& kv : g_graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    g_graphs.clear();
+}
+
+void drop_batch_plans();
+
+uint64_t bits(double x)
+{
+    uint64_t u;
+    std::memcpy(&u, &x, sizeof u);
+    return u;
+}
+
+uint64_t ptrbits(const void* p) { return (uint64_t)reinterpret_cast<uintptr_t>(p); }
+
+// Captures `body(stream)` once per key and launches the instantiated graph on
+// `stream`.  body must only enqueue kernels.
+template <typename F>
+int run_graph(const GraphKey& key, hipStream_t stream, F&& body)
+{
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_graphs.find(key);
+        if (it != g_graphs.end()) exec = it->second.exec;
+    }
+    if (!exec) {
+        hipStream_t cs = nullptr;
+        NB_TRY(capture_stream(&cs));
+        NB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        const int st = body(cs);
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(cs, &g);
+        if (st != NBODY_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (ee != hipSuccess) return fail(NBODY_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ee));
+        hipGraphExec_t ge = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return fail(NBODY_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+        }
+        std::lock_guard<std::mutex> lk(g_mu);
+        GraphEntry e;
+        e.graph = g;
+        e.exec = ge;
+        g_graphs[key] = e;
+        exec = ge;
+    }
+    NB_HIP(hipGraphLaunch(exec, stream));
+    return NBODY_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the step loop
+
+// One system (or the concatenated batch) of the kick-drift-kick step loop.
+struct StepPlan {
+    int prec = 0;
+    Tile tile{};
+    int chunks = 1;                 // chunks for the epilogue (single system)
+    int64_t n = 0;
+    double G = 0, dt = 0;
+    const double* mass = nullptr;   // in the working order
+    double* vel = nullptr;          // working velocity
+    double* buf[2] = {nullptr, nullptr};   // position ping-pong
+    double* part = nullptr;
+    uint32_t* flags = nullptr;
+    const int64_t* nmaj = nullptr;
+    // batched
+    const BatchUnit* units = nullptr;
+    int64_t num_units = 0;
+    int grid = 0;
+    const int8_t* bchunks = nullptr;
+};
+
+int force(const StepPlan& P, const double* pos, hipStream_t s)
+{
+    if (P.units)
+        NB_HIP(launch_force_batched(P.prec, P.tile, pos, P.mass, P.n, P.G, P.units, P.num_units,
+                                    P.nmaj, P.grid, P.part, s));
+    else
+        NB_HIP(launch_force(P.prec, P.tile, pos, P.mass, P.n, P.nmaj, P.G, P.part, s));
+    return NBODY_OK;
+}
+
+// Launch i of a run of `steps` steps (i = 0 .. steps): the force pass at r_i
+// (in buf[i & 1]) followed by the epilogue.
+int step_launch(const StepPlan& P, int64_t i, int64_t steps, hipStream_t s)
+{
+    const double* pin = P.buf[i & 1];
+    double* pout = P.buf[(i + 1) & 1];
+    NB_TRY(force(P, pin, s));
+    int mode = 0;
+    if (i > 0) mode |= kClose;
+    if (i < steps) mode |= kOpen;
+    NB_HIP(launch_step(P.part, P.chunks, P.bchunks, P.n, P.vel, pin, pout, nullptr, P.dt, mode,
+                       P.flags, s));
+    return NBODY_OK;
+}
+
+constexpr int64_t kGraphSteps = 64;   // middle steps per captured graph (even)
+
+// Launches 0..steps; r_0 must be in buf[0].  The final r_steps lands in
+// buf[steps & 1].  Middle launches are replayed from a captured graph.
+int run_steps(const StepPlan& P, int64_t steps, hipStream_t stream, bool use_graph)
+{
+    if (steps <= 0) return NBODY_OK;
+    NB_TRY(step_launch(P, 0, steps, stream));
+    int64_t i = 1;
+    const int64_t middle = steps - 1;
+    if (use_graph && middle >= 2 * kGraphSteps) {
+        GraphKey key;
+        key.v = {1, (uint64_t)P.prec, (uint64_t)P.tile.tpl, (uint64_t)P.tile.waves,
+                 (uint64_t)P.tile.chunks, (uint64_t)P.chunks, (uint64_t)P.n, bits(P.G), bits(P.dt),
+                 ptrbits(P.mass), ptrbits(P.vel), ptrbits(P.buf[0]), ptrbits(P.buf[1]),
+                 ptrbits(P.part), ptrbits(P.flags), ptrbits(P.nmaj), ptrbits(P.units),
+                 (uint64_t)P.num_units, (uint64_t)P.grid, ptrbits(P.bchunks)};
+        const int64_t reps = middle / kGraphSteps;
+        for (int64_t r = 0; r < reps; ++r) {
+            // every replay starts at an odd launch index (r_i in buf[1])
+            NB_TRY(run_graph(key, stream, [&](hipStream_t cs) {
+                for (int64_t k = 0; k < kGraphSteps; ++k) {
+                    const int st = step_launch(P, 1 + k, steps, cs);
+                    if (st != NBODY_OK) return st;
+                }
+                return (int)NBODY_OK;
+            }));
+        }
+        i = 1 + reps * kGraphSteps;
+    }
+    for (; i <= steps; ++i) NB_TRY(step_launch(P, i, steps, stream));
+    return NBODY_OK;
+}
+
+int split_prepare(void* ws, const Layout& L, const double* mass, int64_t n, double small_mass,
+                  hipStream_t s)
+{
+    NB_HIP(launch_partition(mass, nullptr, 1, n, small_mass, at<int32_t>(ws, L.perm),
+                            at<int64_t>(ws, L.nmaj), s));
+    return NBODY_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+
+extern "C" {
+
+const char* nbody_last_error(void) { return g_err.c_str(); }
+
+const char* nbody_version(void) { return "nbody-gfx950 1.0"; }
+
+size_t nbody_workspace_bytes(int32_t op, int64_t n_total, int32_t num_systems, int64_t steps,
+                             int64_t checkpoint_every, int32_t precision)
+{
+    if (n_total < 1 || n_total > kMaxBodies || num_systems < 1) return 0;
+    if (op < NBODY_OP_ACCEL || op > NBODY_OP_ENERGY) return 0;
+    if (precision != NBODY_FP64 && precision != NBODY_SPLIT) return 0;
+    if (op == NBODY_OP_ADJOINT && (checkpoint_every < 1 || steps < 0)) return 0;
+    return layout(op, n_total, num_systems, steps, checkpoint_every, precision).total;
+}
+
+int32_t nbody_accel(const double* pos, const double* vel, const double* mass, int64_t n,
+                    double G, double dt, int64_t steps, double* acc_out, int32_t precision,
+                    double small_mass, void* workspace, size_t workspace_bytes, void* stream)
+{
+    (void)vel;
+    (void)dt;
+    (void)steps;
+    g_err.clear();
+    NB_TRY(check_common(pos, mass, n, G));
+    NB_TRY(check_prec(precision, small_mass));
+    if (!acc_out) return fail(NBODY_EINVAL, "acc_out is NULL");
+    const Layout L = layout(NBODY_OP_ACCEL, n, 1, 0, 1, precision);
+    NB_TRY(check_ws(workspace, workspace_bytes, L.total));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Tile tile = pick_tile(0, precision, n);
+    const int chunks = effective_chunks(n, tile);
+    double* part = at<double>(workspace, L.part);
+    uint32_t* flags = at<uint32_t>(workspace, L.flags);
+    if (precision == NBODY_FP64) {
+        NB_HIP(launch_force(0, tile, pos, mass, n, nullptr, G, part, s));
+        NB_HIP(launch_step(part, chunks, nullptr, n, nullptr, nullptr, nullptr, acc_out, 0.0,
+                           kStoreAcc, flags, s));
+        return NBODY_OK;
+    }
+    NB_TRY(split_prepare(workspace, L, mass, n, small_mass, s));
+    const int32_t* perm = at<int32_t>(workspace, L.perm);
+    double* pos_c = at<double>(workspace, L.pos_c);
+    double* mass_c = at<double>(workspace, L.mass_c);
+    double* acc_c = at<double>(workspace, L.alt_c);
+    NB_HIP(launch_gather(perm, n, pos, pos_c, 3, s));
+    NB_HIP(launch_gather(perm, n, mass, mass_c, 1, s));
+    NB_HIP(launch_force(1, tile, pos_c, mass_c, n, at<int64_t>(workspace, L.nmaj), G, part, s));
+    NB_HIP(launch_step(part, chunks, nullptr, n, nullptr, nullptr, nullptr, acc_c, 0.0,
+                       kStoreAcc, flags, s));
+    NB_HIP(launch_scatter(perm, n, acc_c, acc_out, 3, s));
+    return NBODY_OK;
+}
+
+int32_t nbody_verlet_run(double* pos, double* vel, const double* mass, int64_t n, double G,
+                         double dt, int64_t steps, int32_t precision, double small_mass,
+                         void* workspace, size_t workspace_bytes, void* stream)
+{
+    g_err.clear();
+    NB_TRY(check_common(pos, mass, n, G));
+    NB_TRY(check_prec(precision, small_mass));
+    if (!vel) return fail(NBODY_EINVAL, "vel is NULL");
+    if (steps < 0) return fail(NBODY_EINVAL, "steps must be >= 0");
+    if (!std::isfinite(dt)) return fail(NBODY_EINVAL, "dt is not finite");
+    const Layout L = layout(NBODY_OP_RUN, n, 1, steps, 1, precision);
+    NB_TRY(check_ws(workspace, workspace_bytes, L.total));
+    if (steps == 0) return NBODY_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    StepPlan P;
+    P.prec = precision;
+    P.tile = pick_tile(0, precision, n);
+    P.chunks = effective_chunks(n, P.tile);
+    P.n = n;
+    P.G = G;
+    P.dt = dt;
+    P.part = at<double>(workspace, L.part);
+    P.flags = at<uint32_t>(workspace, L.flags);
+    double* alt = at<double>(workspace, L.alt);
+    if (precision == NBODY_FP64) {
+        P.mass = mass;
+        P.vel = vel;
+        // r_steps must land in the caller's buffer: buf[steps & 1] = pos.
+        if (steps & 1) {
+            P.buf[0] = alt;
+            P.buf[1] = pos;
+            NB_HIP(hipMemcpyAsync(alt, pos, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        } else {
+            P.buf[0] = pos;
+            P.buf[1] = alt;
+        }
+        return run_steps(P, steps, s, true);
+    }
+    NB_TRY(split_prepare(workspace, L, mass, n, small_mass, s));
+    const int32_t* perm = at<int32_t>(workspace, L.perm);
+    double* pos_c = at<double>(workspace, L.pos_c);
+    double* vel_c = at<double>(workspace, L.vel_c);
+    double* mass_c = at<double>(workspace, L.mass_c);
+    double* alt_c = at<double>(workspace, L.alt_c);
+    NB_HIP(launch_gather(perm, n, pos, pos_c, 3, s));
+    NB_HIP(launch_gather(perm, n, vel, vel_c, 3, s));
+    NB_HIP(launch_gather(perm, n, mass, mass_c, 1, s));
+    P.mass = mass_c;
+    P.vel = vel_c;
+    P.buf[0] = pos_c;
+    P.buf[1] = alt_c;
+    P.nmaj = at<int64_t>(workspace, L.nmaj);
+    NB_TRY(run_steps(P, steps, s, true));
+    NB_HIP(launch_scatter(perm, n, P.buf[steps & 1], pos, 3, s));
+    NB_HIP(launch_scatter(perm, n, vel_c, vel, 3, s));
+    return NBODY_OK;
+}
+
+int32_t nbody_energy(const double* pos, const double* vel, const double* mass, int64_t n,
+                     double G, double* out, void* workspace, size_t workspace_bytes, void* stream)
+{
+    g_err.clear();
+    NB_TRY(check_common(pos, mass, n, G));
+    if (!vel || !out) return fail(NBODY_EINVAL, "vel or out is NULL");
+    const Layout L = layout(NBODY_OP_ENERGY, n, 1, 0, 1, NBODY_FP64);
+    NB_TRY(check_ws(workspace, workspace_bytes, L.total));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* rows = at<double>(workspace, L.rows);
+    NB_HIP(launch_potential_rows(pos, mass, n, G, rows, s));
+    NB_HIP(launch_energy_finish(rows, vel, mass, n, out, s));
+    return NBODY_OK;
+}
+
+int32_t nbody_momenta(const double* pos, const double* vel, const double* mass, int64_t n,
+                      double* out, void* stream)
+{
+    g_err.clear();
+    NB_TRY(check_common(pos, mass, n, 1.0));
+    if (!vel || !out) return fail(NBODY_EINVAL, "vel or out is NULL");
+    NB_HIP(launch_momenta(pos, vel, mass, n, out, static_cast<hipStream_t>(stream)));
+    return NBODY_OK;
+}
+
+int32_t nbody_get_flags(void* workspace, void* stream, int32_t clear, int32_t* flags_host)
+{
+    g_err.clear();
+    if (!workspace || !flags_host) return fail(NBODY_EINVAL, "null workspace or flags pointer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t v = 0;
+    NB_HIP(hipMemcpyAsync(&v, workspace, sizeof v, hipMemcpyDeviceToHost, s));
+    NB_HIP(hipStreamSynchronize(s));
+    *flags_host = (int32_t)v;
+    if (clear) {
+        NB_HIP(hipMemsetAsync(workspace, 0, sizeof(uint32_t), s));
+        NB_HIP(hipStreamSynchronize(s));
+    }
+    return NBODY_OK;
+}
+
+int32_t nbody_get_tile(int32_t kind, int32_t precision, int64_t n, nbody_tile* tile_host)
+{
+    g_err.clear();
+    if (!tile_host || (kind != 0 && kind != 1) || n < 1) return fail(NBODY_EINVAL, "bad arguments");
+    const Tile t = pick_tile(kind, precision, n);
+    tile_host->targets_per_lane = t.tpl;
+    tile_host->waves = t.waves;
+    tile_host->chunks = t.chunks;
+    return NBODY_OK;
+}
+
+int32_t nbody_set_tile(int32_t kind, int32_t precision, int64_t n, const nbody_tile* tile_host)
+{
+    g_err.clear();
+    if (!tile_host || (kind != 0 && kind != 1) || n < 1) return fail(NBODY_EINVAL, "bad arguments");
+    Tile t{tile_host->targets_per_lane, tile_host->waves, tile_host->chunks};
+    if (!tile_supported(t) || (kind == 1 && (t.tpl > 2 || t.waves > 4)))
+        return fail(NBODY_EINVAL, "unsupported tile (%d, %d, %d)", t.tpl, t.waves, t.chunks);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tiles[std::make_tuple(kind, precision, size_class(n))] = t;
+    return NBODY_OK;
+}
+
+void nbody_reset_caches(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tiles.clear();
+    drop_graphs();
+    drop_batch_plans();
+}
+
+int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const double* mass, int64_t n,
+                             double G, double dt, int64_t steps, int64_t checkpoint_every,
+                             const double* grad_posT, const double* grad_velT, double* grad_pos0,
+                             double* grad_vel0, double* grad_mass, double* pos_out,
+                             double* vel_out, void* workspace, size_t workspace_bytes,
+                             void* stream)
+{
+    g_err.clear();
+    NB_TRY(check_common(pos0, mass, n, G));
+    if (!vel0 || !grad_posT || !grad_velT || !grad_pos0 || !grad_vel0 || !grad_mass)
+        return fail(NBODY_EINVAL, "null velocity, cotangent or gradient pointer");
+    if (steps < 0) return fail(NBODY_EINVAL, "steps must be >= 0");
+    if (checkpoint_every < 1) return fail(NBODY_EINVAL, "checkpoint_every must be >= 1");
+    if (!std::isfinite(dt)) return fail(NBODY_EINVAL, "dt is not finite");
+    const Layout L = layout(NBODY_OP_ADJOINT, n, 1, steps, checkpoint_every, NBODY_FP64);
+    NB_TRY(check_ws(workspace, workspace_bytes, L.total));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t b3 = 3 * n * sizeof(double);
+    const int64_t K = checkpoint_every;
+    const int64_t nck = (steps + K - 1) / K;
+    double* ck = at<double>(workspace, L.ck);
+    double* seg = at<double>(workspace, L.seg);
+    double* alt = at<double>(workspace, L.alt);
+    double* lam_r = at<double>(workspace, L.lam_r);
+    double* lam_v = at<double>(workspace, L.lam_v);
+    double* g_m = at<double>(workspace, L.g_m);
+    double* u = at<double>(workspace, L.u);
+    double* vtmp = at<double>(workspace, L.vtmp);
+    double* part = at<double>(workspace, L.part);
+    uint32_t* flags = at<uint32_t>(workspace, L.flags);
+    auto ck_r = [&](int64_t k) { return ck + k * 6 * n; };
+    auto ck_v = [&](int64_t k) { return ck + k * 6 * n + 3 * n; };
+
+    // Forward run, storing (r, v) every K steps.  Each segment is a complete
+    // run of nbody_verlet_run, so segments chain bit for bit.
+    StepPlan P;
+    P.prec = NBODY_FP64;
+    P.tile = pick_tile(0, NBODY_FP64, n);
+    P.chunks = effective_chunks(n, P.tile);
+    P.n = n;
+    P.G = G;
+    P.dt = dt;
+    P.mass = mass;
+    P.part = part;
+    P.flags = flags;
+    NB_HIP(hipMemcpyAsync(ck_r(0), pos0, b3, hipMemcpyDeviceToDevice, s));
+    NB_HIP(hipMemcpyAsync(ck_v(0), vel0, b3, hipMemcpyDeviceToDevice, s));
+    for (int64_t c = 0; c < nck; ++c) {
+        const int64_t kseg = std::min(K, steps - c * K);
+        NB_HIP(hipMemcpyAsync(ck_r(c + 1), ck_r(c), 2 * b3, hipMemcpyDeviceToDevice, s));
+        P.vel = ck_v(c + 1);
+        if (kseg & 1) {
+            NB_HIP(hipMemcpyAsync(alt, ck_r(c + 1), b3, hipMemcpyDeviceToDevice, s));
+            P.buf[0] = alt;
+            P.buf[1] = ck_r(c + 1);
+        } else {
+            P.buf[0] = ck_r(c + 1);
+            P.buf[1] = alt;
+        }
+        NB_TRY(run_steps(P, kseg, s, false));
+    }
+    if (pos_out) NB_HIP(hipMemcpyAsync(pos_out, ck_r(nck), b3, hipMemcpyDeviceToDevice, s));
+    if (vel_out) NB_HIP(hipMemcpyAsync(vel_out, ck_v(nck), b3, hipMemcpyDeviceToDevice, s));
+
+    // Reverse sweep (one transpose-Jacobian product of Eq. (1) per force pass).
+    const Tile vt = pick_tile(1, NBODY_FP64, n);
+    const int vchunks = effective_chunks(n, vt);
+    NB_HIP(hipMemcpyAsync(lam_r, grad_posT, b3, hipMemcpyDeviceToDevice, s));
+    NB_HIP(hipMemcpyAsync(lam_v, grad_velT, b3, hipMemcpyDeviceToDevice, s));
+    NB_HIP(launch_fill(g_m, 0.0, n, s));
+    auto vjp_into = [&](const double* r) -> int {
+        NB_HIP(launch_vjp(vt, r, mass, u, n, G, part, s));
+        NB_HIP(launch_vjp_reduce(part, vchunks, n, lam_r, g_m, s));
+        return NBODY_OK;
+    };
+    if (steps > 0) {
+        // closing half kick of the last step: v_T = v_{T-1/2} + dt/2 a(r_T)
+        NB_HIP(launch_scale(lam_v, 0.5 * dt, 3 * n, u, s));
+        NB_TRY(vjp_into(ck_r(nck)));
+    }
+    StepPlan R = P;   // recompute plan: positions of one segment into seg slots
+    R.vel = vtmp;
+    for (int64_t c = nck - 1; c >= 0; --c) {
+        const int64_t kseg = std::min(K, steps - c * K);
+        NB_HIP(hipMemcpyAsync(seg, ck_r(c), b3, hipMemcpyDeviceToDevice, s));
+        NB_HIP(hipMemcpyAsync(vtmp, ck_v(c), b3, hipMemcpyDeviceToDevice, s));
+        for (int64_t k = 0; k + 1 < kseg; ++k) {
+            double* pin = seg + k * 3 * n;
+            NB_TRY(force(R, pin, s));
+            const int mode = (k > 0 ? kClose : 0) | kOpen;
+            NB_HIP(launch_step(part, R.chunks, nullptr, n, vtmp, pin, pin + 3 * n, nullptr, dt,
+                               mode, flags, s));
+        }
+        for (int64_t k = kseg - 1; k >= 0; --k) {
+            const int64_t i = c * K + k;
+            // drift r_{i+1} = r_i + dt v_{i+1/2}
+            NB_HIP(launch_axpy(lam_r, dt, 3 * n, lam_v, s));
+            // kick v_{i+1/2} = v_{i-1/2} + dt a(r_i)   (dt/2 for i = 0)
+            NB_HIP(launch_scale(lam_v, i > 0 ? dt : 0.5 * dt, 3 * n, u, s));
+            NB_TRY(vjp_into(seg + k * 3 * n));
+        }
+    }
+    NB_HIP(hipMemcpyAsync(grad_pos0, lam_r, b3, hipMemcpyDeviceToDevice, s));
+    NB_HIP(hipMemcpyAsync(grad_vel0, lam_v, b3, hipMemcpyDeviceToDevice, s));
+    NB_HIP(hipMemcpyAsync(grad_mass, g_m, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return NBODY_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Work list of the batched launch, cached per (offsets, tile).
+struct BatchPlan {
+    std::vector<BatchUnit> units;
+    std::vector<int8_t> bchunks;
+    std::vector<int64_t> offsets;
+};
+
+std::map<std::vector<int64_t>, std::shared_ptr<BatchPlan>> g_batch;
+
+void drop_batch_plans() { g_batch.clear(); }
+
+constexpr int64_t kBatchChunkLen = 1024;   // sources per chunk in the ensemble
+
+std::shared_ptr<BatchPlan> batch_plan(const int64_t* offs, int32_t ns, const Tile& t)
+{
+    std::vector<int64_t> key(offs, offs + ns + 1);
+    key.push_back(t.tpl);
+    key.push_back(t.waves);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_batch.find(key);
+    if (it != g_batch.end()) return it->second;
+    auto bp = std::make_shared<BatchPlan>();
+    bp->offsets.assign(offs, offs + ns + 1);
+    const int64_t n_total = offs[ns];
+    bp->bchunks.resize(n_total);
+    const int64_t tb_size = 64 * (int64_t)t.waves * t.tpl;
+    for (int32_t k = 0; k < ns; ++k) {
+        const int64_t nk = offs[k + 1] - offs[k];
+        const int chunks = (int)std::min<int64_t>(kBatchChunkMax,
+                                                  std::max<int64_t>(1, (nk + kBatchChunkLen - 1) / kBatchChunkLen));
+        Tile tk = t;
+        tk.chunks = chunks;
+        const int eff = effective_chunks(nk, tk);
+        const int64_t tblocks = (nk + tb_size - 1) / tb_size;
+        for (int64_t b = 0; b < tblocks; ++b)
+            for (int c = 0; c < eff; ++c) {
+                BatchUnit u;
+                u.body0 = offs[k];
+                u.n = (int32_t)nk;
+                u.sys = k;
+                u.tblock = (int32_t)b;
+                u.chunk = c;
+                u.chunks = chunks;
+                u.pad = 0;
+                bp->units.push_back(u);
+            }
+        std::fill(bp->bchunks.begin() + offs[k], bp->bchunks.begin() + offs[k + 1], (int8_t)eff);
+    }
+    // Largest systems first, so the persistent grid's static round-robin over
+    // the list ends with the cheap units.
+    std::stable_sort(bp->units.begin(), bp->units.end(),
+                     [](const BatchUnit& a, const BatchUnit& b) { return a.n > b.n; });
+    g_batch[key] = bp;
+    return bp;
+}
+
+int device_cus(int* cus)
+{
+    int dev = 0;
+    NB_HIP(hipGetDevice(&dev));
+    NB_HIP(hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev));
+    return NBODY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t nbody_verlet_run_batched(double* pos, double* vel, const double* mass,
+                                 const int64_t* offsets_host, int32_t num_systems, double G,
+                                 double dt, int64_t steps, int32_t precision, double small_mass,
+                                 void* workspace, size_t workspace_bytes, void* stream)
+{
+    g_err.clear();
+    if (!offsets_host || num_systems < 1) return fail(NBODY_EINVAL, "need offsets and >= 1 system");
+    if (offsets_host[0] != 0) return fail(NBODY_EINVAL, "offsets[0] must be 0");
+    for (int32_t k = 0; k < num_systems; ++k)
+        if (offsets_host[k + 1] <= offsets_host[k])
+            return fail(NBODY_EINVAL, "system %d is empty or offsets decrease", k);
+    const int64_t n = offsets_host[num_systems];
+    NB_TRY(check_common(pos, mass, n, G));
+    NB_TRY(check_prec(precision, small_mass));
+    if (!vel) return fail(NBODY_EINVAL, "vel is NULL");
+    if (steps < 0) return fail(NBODY_EINVAL, "steps must be >= 0");
+    if (!std::isfinite(dt)) return fail(NBODY_EINVAL, "dt is not finite");
+    for (int32_t k = 0; k < num_systems; ++k)
+        if (offsets_host[k + 1] - offsets_host[k] > ((int64_t)1 << 24))
+            return fail(NBODY_EUNSUPPORTED, "system %d has more than 2^24 bodies", k);
+    const Layout L = layout(NBODY_OP_BATCHED, n, num_systems, steps, 1, precision);
+    NB_TRY(check_ws(workspace, workspace_bytes, L.total));
+    if (steps == 0) return NBODY_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    Tile t = pick_tile(2, precision, 0);
+    const auto bp = batch_plan(offsets_host, num_systems, t);
+    BatchUnit* units = at<BatchUnit>(workspace, L.units);
+    int8_t* bchunks = at<int8_t>(workspace, L.bchunks);
+    int64_t* offs = at<int64_t>(workspace, L.offs);
+    NB_HIP(hipMemcpyAsync(units, bp->units.data(), bp->units.size() * sizeof(BatchUnit),
+                          hipMemcpyHostToDevice, s));
+    NB_HIP(hipMemcpyAsync(bchunks, bp->bchunks.data(), n, hipMemcpyHostToDevice, s));
+    NB_HIP(hipMemcpyAsync(offs, bp->offsets.data(), (num_systems + 1) * sizeof(int64_t),
+                          hipMemcpyHostToDevice, s));
+    int cus = 0;
+    NB_TRY(device_cus(&cus));
+
+    StepPlan P;
+    P.prec = precision;
+    P.tile = t;
+    P.chunks = 0;
+    P.n = n;
+    P.G = G;
+    P.dt = dt;
+    P.part = at<double>(workspace, L.part);
+    P.flags = at<uint32_t>(workspace, L.flags);
+    P.units = units;
+    P.num_units = (int64_t)bp->units.size();
+    P.grid = (int)std::min<int64_t>(P.num_units, (int64_t)cus * (16 / t.waves));
+    P.bchunks = bchunks;
+    double* alt = at<double>(workspace, L.alt);
+    if (precision == NBODY_FP64) {
+        P.mass = mass;
+        P.vel = vel;
+        if (steps & 1) {
+            P.buf[0] = alt;
+            P.buf[1] = pos;
+            NB_HIP(hipMemcpyAsync(alt, pos, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        } else {
+            P.buf[0] = pos;
+            P.buf[1] = alt;
+        }
+        return run_steps(P, steps, s, true);
+    }
+    NB_HIP(launch_partition(mass, offs, num_systems, 0, small_mass, at<int32_t>(workspace, L.perm),
+                            at<int64_t>(workspace, L.nmaj), s));
+    const int32_t* perm = at<int32_t>(workspace, L.perm);
+    double* pos_c = at<double>(workspace, L.pos_c);
+    double* vel_c = at<double>(workspace, L.vel_c);
+    double* mass_c = at<double>(workspace, L.mass_c);
+    double* alt_c = at<double>(workspace, L.alt_c);
+    NB_HIP(launch_gather(perm, n, pos, pos_c, 3, s));
+    NB_HIP(launch_gather(perm, n, vel, vel_c, 3, s));
+    NB_HIP(launch_gather(perm, n, mass, mass_c, 1, s));
+    P.mass = mass_c;
+    P.vel = vel_c;
+    P.buf[0] = pos_c;
+    P.buf[1] = alt_c;
+    P.nmaj = at<int64_t>(workspace, L.nmaj);
+    NB_TRY(run_steps(P, steps, s, true));
+    NB_HIP(launch_scatter(perm, n, P.buf[steps & 1], pos, 3, s));
+    NB_HIP(launch_scatter(perm, n, vel_c, vel, 3, s));
+    return NBODY_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Working data of a timed force pass (class order for the split form).
+struct Bench {
+    const double* pos = nullptr;
+    const double* mass = nullptr;
+    const int64_t* nmaj = nullptr;
+    double* part = nullptr;
+    double* scratch = nullptr;
+};
+
+int bench_prepare(int32_t kind, int32_t precision, const double* pos, const double* mass,
+                  int64_t n, double G, double small_mass, void* workspace,
+                  size_t workspace_bytes, hipStream_t s, Bench* b)
+{
+    NB_TRY(check_common(pos, mass, n, G));
+    NB_TRY(check_prec(precision, small_mass));
+    if (kind != 0 && kind != 1) return fail(NBODY_EINVAL, "kind must be 0 or 1");
+    if (kind == 1 && precision != NBODY_FP64) return fail(NBODY_EINVAL, "the adjoint pass is FP64");
+    const int op = kind == 0 ? NBODY_OP_ACCEL : NBODY_OP_ADJOINT;
+    const Layout L = layout(op, n, 1, 1, 1, precision);
+    NB_TRY(check_ws(workspace, workspace_bytes, L.total));
+    b->part = at<double>(workspace, L.part);
+    b->scratch = at<double>(workspace, L.alt);
+    b->pos = pos;
+    b->mass = mass;
+    if (precision == NBODY_SPLIT) {
+        NB_TRY(split_prepare(workspace, L, mass, n, small_mass, s));
+        const int32_t* perm = at<int32_t>(workspace, L.perm);
+        NB_HIP(launch_gather(perm, n, pos, at<double>(workspace, L.pos_c), 3, s));
+        NB_HIP(launch_gather(perm, n, mass, at<double>(workspace, L.mass_c), 1, s));
+        b->pos = at<double>(workspace, L.pos_c);
+        b->mass = at<double>(workspace, L.mass_c);
+        b->nmaj = at<int64_t>(workspace, L.nmaj);
+    }
+    if (kind == 1) NB_HIP(launch_fill(b->scratch, 1e-3, 3 * n, s));   // cotangent for timing
+    return NBODY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t nbody_time_force(int32_t kind, int32_t precision, const double* pos, const double* mass,
+                         int64_t n, double G, double small_mass, int32_t reps, void* workspace,
+                         size_t workspace_bytes, void* stream, double* ms_per_pass_host)
+{
+    g_err.clear();
+    if (reps < 1 || !ms_per_pass_host) return fail(NBODY_EINVAL, "reps < 1 or null output");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Bench b;
+    NB_TRY(bench_prepare(kind, precision, pos, mass, n, G, small_mass, workspace, workspace_bytes,
+                         s, &b));
+    const Tile t = pick_tile(kind, precision, n);
+    auto once = [&]() -> int {
+        if (kind == 0) NB_HIP(launch_force(precision, t, b.pos, b.mass, n, b.nmaj, G, b.part, s));
+        else           NB_HIP(launch_vjp(t, b.pos, b.mass, b.scratch, n, G, b.part, s));
+        return NBODY_OK;
+    };
+    NB_TRY(once());
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    NB_HIP(hipEventCreate(&e0));
+    NB_HIP(hipEventCreate(&e1));
+    int st = NBODY_OK;
+    if (hipEventRecord(e0, s) != hipSuccess) st = fail(NBODY_EHIP, "hipEventRecord failed");
+    for (int r = 0; r < reps && st == NBODY_OK; ++r) st = once();
+    if (st == NBODY_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+        st = fail(NBODY_EHIP, "event timing failed");
+    float ms = 0.f;
+    if (st == NBODY_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != NBODY_OK) return st;
+    *ms_per_pass_host = (double)ms / reps;
+    return NBODY_OK;
+}
+
+int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const double* mass,
+                       int64_t n, double G, double small_mass, void* workspace,
+                       size_t workspace_bytes, void* stream, nbody_tile* best_host,
+                       double* best_ms_host)
+{
+    g_err.clear();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Bench b;
+    NB_TRY(bench_prepare(kind, precision, pos, mass, n, G, small_mass, workspace, workspace_bytes,
+                         s, &b));
+    double* part = b.part;
+    double* scratch = b.scratch;
+    const double* pos_w = b.pos;
+    const double* mass_w = b.mass;
+    const int64_t* nmaj = b.nmaj;
+
+    // candidates
+    std::vector<Tile> cands;
+    const int tpls[3] = {1, 2, 4};
+    const int waves[4] = {1, 2, 4, 8};
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 4; ++b) {
+            Tile t{tpls[a], waves[b], 1};
+            if (kind == 1 && (t.tpl > 2 || t.waves > 4)) continue;
+            const int64_t tb = (n + 64 * t.waves * t.tpl - 1) / (64 * t.waves * t.tpl);
+            std::vector<int> cs = {1};
+            for (int64_t target : {512, 1024, 2048, 3072, 4096, 6144, 8192}) {
+                const int64_t waves_per_chunk = tb * t.waves;
+                int64_t c = target / std::max<int64_t>(waves_per_chunk, 1);
+                c = std::min<int64_t>(c, chunk_cap(n));
+                c = std::min<int64_t>(c, std::max<int64_t>(1, n / (64 * t.waves)));
+                if (c >= 1) cs.push_back((int)c);
+            }
+            std::sort(cs.begin(), cs.end());
+            cs.erase(std::unique(cs.begin(), cs.end()), cs.end());
+            for (int c : cs) cands.push_back(Tile{t.tpl, t.waves, c});
+        }
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    NB_HIP(hipEventCreate(&e0));
+    NB_HIP(hipEventCreate(&e1));
+    auto once = [&](const Tile& t) -> int {
+        if (kind == 0) {
+            NB_HIP(launch_force(precision, t, pos_w, mass_w, n, nmaj, G, part, s));
+            NB_HIP(launch_step(part, effective_chunks(n, t), nullptr, n, nullptr, nullptr, nullptr,
+                               scratch, 0.0, kStoreAcc, nullptr, s));
+        } else {
+            NB_HIP(launch_vjp(t, pos_w, mass_w, scratch, n, G, part, s));
+        }
+        return NBODY_OK;
+    };
+    // repetitions so that each measurement covers at least ~2 ms of work
+    const double pairs = (double)n * (double)n;
+    const int reps = (int)std::max(3.0, std::min(200.0, 2e9 / std::max(pairs, 1.0)));
+    Tile best = cands.front();
+    float best_ms = 1e30f;
+    int status = NBODY_OK;
+    for (const Tile& t : cands) {
+        if ((status = once(t)) != NBODY_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { status = fail(NBODY_EHIP, "event record"); break; }
+        for (int r = 0; r < reps && status == NBODY_OK; ++r) status = once(t);
+        if (status != NBODY_OK) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            status = fail(NBODY_EHIP, "event sync");
+            break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status != NBODY_OK) return status;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_tiles[std::make_tuple(kind, precision, size_class(n))] = best;
+    }
+    if (best_host) {
+        best_host->targets_per_lane = best.tpl;
+        best_host->waves = best.waves;
+        best_host->chunks = best.chunks;
+    }
+    if (best_ms_host) *best_ms_host = best_ms;
+    return NBODY_OK;
+}
+
+}  // extern "C"

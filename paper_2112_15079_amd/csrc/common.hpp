@@ -1,0 +1,106 @@
+// Shared declarations of the HIP library: the tile shape, the per-launch
+// argument blocks and the host-side launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nb {
+
+// Shape of one force launch.  A workgroup of 64*waves lanes owns
+// 64*waves*tpl consecutive targets; lane l of the group handles targets
+// base + t*64*waves + l for t < tpl, so every target plane is loaded and
+// stored with unit stride.  The source range is split into `chunks`
+// contiguous pieces (grid.y), each summed separately; the step epilogue adds
+// the pieces in a fixed order, so results do not depend on scheduling.
+struct Tile {
+    int tpl;     // targets per lane: 1, 2, 4
+    int waves;   // wavefronts per workgroup: 1, 2, 4, 8
+    int chunks;  // source chunks, 1..64
+};
+
+constexpr int kMaxChunks = 64;
+
+// Source tile width (bodies staged in LDS per pass) = lanes of a workgroup.
+inline int tile_width(const Tile& t) { return 64 * t.waves; }
+
+bool tile_supported(const Tile& t);
+
+// Length of each source chunk: a multiple of the tile width so that only the
+// very last tile of the last chunk holds padding.
+int64_t chunk_length(int64_t n, const Tile& t);
+// Chunks actually used for n bodies (<= t.chunks).
+int effective_chunks(int64_t n, const Tile& t);
+
+// ----- force pass (Eq. (1)) ------------------------------------------------
+// part[c*3n + k*n + p] receives the chunk-c partial of component k of a_p.
+// Split form: sources [0, n_major) are accumulated in FP64 with a single
+// Newton-refined reciprocal square root, sources [n_major, n) in FP32 with
+// Kahan compensation.
+// nmaj: device pointer to the number of FP64-class sources (split form only).
+hipError_t launch_force(int precision, const Tile& tile, const double* pos, const double* mass,
+                        int64_t n, const int64_t* nmaj, double G, double* part, hipStream_t s);
+
+// Batched form: `units` work items of (system, target block, chunk), see
+// kernels_force.hip.
+struct BatchUnit {
+    int64_t body0;     // first body of the system
+    int32_t n;         // bodies in the system
+    int32_t sys;       // system index (split form: nmaj[sys] FP64-class sources first)
+    int32_t tblock;    // target block within the system
+    int32_t chunk;     // chunk index
+    int32_t chunks;    // chunks of this system
+    int32_t pad;
+};
+hipError_t launch_force_batched(int precision, const Tile& tile, const double* pos,
+                                const double* mass, int64_t n_total, double G,
+                                const BatchUnit* units, int64_t num_units, const int64_t* nmaj,
+                                int grid, double* part, hipStream_t s);
+
+// ----- step epilogue (Eqs. (3)-(4) as kick-drift-kick) -----------------------
+enum StepMode : int {
+    kStoreAcc = 1,   // write a to acc
+    kClose = 2,      // v += dt/2 a  (closing half kick of the step that ends here)
+    kOpen = 4,       // v += dt/2 a; r_out = r_in + dt v  (next step's kick + drift)
+};
+// a_p = sum_{c < chunks_of(p)} part[c][.][p] in ascending c, then the mode's
+// updates.  chunks_of(p) = chunks, or body_chunks[p] when that is not NULL.
+hipError_t launch_step(const double* part, int chunks, const int8_t* body_chunks, int64_t n,
+                       double* vel, const double* pos_in, double* pos_out, double* acc,
+                       double dt, int mode, uint32_t* flags, hipStream_t s);
+
+// ----- split form: class order -------------------------------------------------
+// Stable partition of each system's bodies into mass >= threshold first:
+// perm[body0 + i] = original index of the i-th body in class order, and
+// nmaj[k] = number of FP64-class bodies of system k.  offsets: device array of
+// num_systems + 1 body offsets, or NULL for one system of n_single bodies.
+hipError_t launch_partition(const double* mass, const int64_t* offsets, int num_systems,
+                            int64_t n_single, double threshold, int32_t* perm, int64_t* nmaj,
+                            hipStream_t s);
+hipError_t launch_gather(const int32_t* perm, int64_t n, const double* src3, double* dst3,
+                         int planes, hipStream_t s);
+hipError_t launch_scatter(const int32_t* perm, int64_t n, const double* src3, double* dst3,
+                          int planes, hipStream_t s);
+
+// ----- diagnostics -------------------------------------------------------------
+hipError_t launch_potential_rows(const double* pos, const double* mass, int64_t n, double G,
+                                 double* rows, hipStream_t s);
+hipError_t launch_energy_finish(const double* rows, const double* vel, const double* mass,
+                                int64_t n, double* out, hipStream_t s);
+hipError_t launch_momenta(const double* pos, const double* vel, const double* mass, int64_t n,
+                          double* out, hipStream_t s);
+
+// ----- adjoint (transpose of the Jacobian of Eq. (1)) ------------------------------
+// For cotangent u (on accelerations): lam_r[q] += (J^T u)_q, g_m[q] += (M^T u)_q.
+hipError_t launch_vjp(const Tile& tile, const double* pos, const double* mass, const double* u,
+                      int64_t n, double G, double* part, hipStream_t s);
+// lam_r += sum of chunk partials (planes 0..2), g_m += plane 3.
+hipError_t launch_vjp_reduce(const double* part, int chunks, int64_t n, double* lam_r,
+                             double* g_m, hipStream_t s);
+// u = c * lam_v
+hipError_t launch_scale(const double* x, double c, int64_t m, double* y, hipStream_t s);
+// y += c * x
+hipError_t launch_axpy(const double* x, double c, int64_t m, double* y, hipStream_t s);
+hipError_t launch_fill(double* y, double v, int64_t m, hipStream_t s);
+
+}  // namespace nb

@@ -1,0 +1,227 @@
+// Transpose of the Jacobian of Eq. (1), the inner operation of the discrete
+// adjoint of the velocity-Verlet trajectory.
+//
+// With d_qj = r_j - r_q and the tidal tensor K(d) = I/|d|^3 - 3 d d^T/|d|^5
+// (symmetric, even in d), the Jacobian blocks of Eq. (1) are
+//   d a_p/d r_q = G m_q K(d_pq)  (q != p),   d a_p/d r_p = -sum_j G m_j K(d_pj),
+//   d a_p/d m_q = G d_pq / |d_pq|^3.
+// For a cotangent u on the accelerations this gives, per body q,
+//   (J^T u)_q = G sum_{j != q} K(d_qj) (m_q u_j - m_j u_q)
+//   (M^T u)_q = -G sum_{j != q} u_j . d_qj / |d_qj|^3,
+// one all-pairs pass over (r, m, u) with the same tiling as the force pass.
+#include "common.hpp"
+
+namespace nb {
+namespace {
+
+struct __attribute__((aligned(64))) ASrc {
+    double x, y, z, m, ux, uy, uz, pad;
+};
+
+constexpr double kPad = 1.0e18;
+
+// 1/r to full FP64 accuracy (see the force pass): y0 from the FP32 reciprocal
+// square root, e = 1 - r2 y0^2, 1/r = y0 (1 + e/2 + 3/8 e^2 + O(e^3)).
+__device__ __forceinline__ double rinv_f64(double r2)
+{
+    const double y = (double)__builtin_amdgcn_rsqf((float)r2);
+    const double e = __builtin_fma(-r2, y * y, 1.0);
+    return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
+}
+
+template <int T, int W, bool MASK>
+__device__ __forceinline__ void vjp_sweep(const ASrc* __restrict__ tile, int j0,
+                                          const double (&qx)[T], const double (&qy)[T],
+                                          const double (&qz)[T], const double (&qm)[T],
+                                          const double (&ux)[T], const double (&uy)[T],
+                                          const double (&uz)[T], const int (&qid)[T],
+                                          double (&ox)[T], double (&oy)[T], double (&oz)[T],
+                                          double (&og)[T])
+{
+    constexpr int NT = 64 * W;
+#pragma unroll 2
+    for (int jj = 0; jj < NT; ++jj) {
+        const ASrc s = tile[jj];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const double dx = s.x - qx[t];
+            const double dy = s.y - qy[t];
+            const double dz = s.z - qz[t];
+            const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+            const double y = rinv_f64(r2);
+            const double y2 = y * y;
+            double i3 = y * y2;
+            double i5 = i3 * y2;
+            if (MASK) {
+                const bool self = (j0 + jj == qid[t]);
+                i3 = self ? 0.0 : i3;
+                i5 = self ? 0.0 : i5;
+            }
+            // w = m_q u_j - m_j u_q
+            const double wx = __builtin_fma(-s.m, ux[t], qm[t] * s.ux);
+            const double wy = __builtin_fma(-s.m, uy[t], qm[t] * s.uy);
+            const double wz = __builtin_fma(-s.m, uz[t], qm[t] * s.uz);
+            const double dw = __builtin_fma(dz, wz, __builtin_fma(dy, wy, dx * wx));
+            const double c = 3.0 * dw * i5;
+            ox[t] = __builtin_fma(-c, dx, __builtin_fma(wx, i3, ox[t]));
+            oy[t] = __builtin_fma(-c, dy, __builtin_fma(wy, i3, oy[t]));
+            oz[t] = __builtin_fma(-c, dz, __builtin_fma(wz, i3, oz[t]));
+            const double ud = __builtin_fma(s.uz, dz, __builtin_fma(s.uy, dy, s.ux * dx));
+            og[t] = __builtin_fma(ud, i3, og[t]);
+        }
+    }
+}
+
+// part[c*4n + k*n + q]: chunk-c partials of G (K (m_q u_j - m_j u_q)) (k < 3)
+// and of -G u_j . d / |d|^3 (k = 3).
+template <int T, int W>
+__global__ __launch_bounds__(64 * W) void k_vjp(const double* __restrict__ pos,
+                                                const double* __restrict__ mass,
+                                                const double* __restrict__ u, int64_t n,
+                                                int64_t chunk_len, double G,
+                                                double* __restrict__ part)
+{
+    constexpr int NT = 64 * W;
+    __shared__ ASrc tile[NT];
+    const int tid = threadIdx.x;
+    const int64_t tb0 = (int64_t)blockIdx.x * NT * T;
+    const int64_t c = blockIdx.y;
+    const int64_t jbeg = c * chunk_len;
+    const int64_t jend = (jbeg + chunk_len < n) ? jbeg + chunk_len : n;
+
+    double qx[T], qy[T], qz[T], qm[T], ux[T], uy[T], uz[T];
+    double ox[T], oy[T], oz[T], og[T];
+    int qid[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int64_t p = tb0 + (int64_t)t * NT + tid;
+        const int64_t q = p < n ? p : n - 1;
+        qid[t] = (int)p;
+        qx[t] = pos[q]; qy[t] = pos[n + q]; qz[t] = pos[2 * n + q];
+        qm[t] = mass[q];
+        ux[t] = u[q]; uy[t] = u[n + q]; uz[t] = u[2 * n + q];
+        ox[t] = 0.0; oy[t] = 0.0; oz[t] = 0.0; og[t] = 0.0;
+    }
+    const int64_t tend = tb0 + (int64_t)NT * T;
+    for (int64_t j0 = jbeg; j0 < jend; j0 += NT) {
+        const int64_t j = j0 + tid;
+        ASrc s;
+        if (j < jend) {
+            s.x = pos[j]; s.y = pos[n + j]; s.z = pos[2 * n + j];
+            s.m = mass[j];
+            s.ux = u[j]; s.uy = u[n + j]; s.uz = u[2 * n + j];
+        } else {
+            s.x = kPad; s.y = kPad; s.z = kPad;
+            s.m = 0.0; s.ux = 0.0; s.uy = 0.0; s.uz = 0.0;
+        }
+        s.pad = 0.0;
+        __syncthreads();
+        tile[tid] = s;
+        __syncthreads();
+        const bool diag = (j0 < tend) && (tb0 < j0 + NT);
+        if (diag) vjp_sweep<T, W, true>(tile, (int)j0, qx, qy, qz, qm, ux, uy, uz, qid, ox, oy, oz, og);
+        else      vjp_sweep<T, W, false>(tile, (int)j0, qx, qy, qz, qm, ux, uy, uz, qid, ox, oy, oz, og);
+    }
+    double* pc = part + c * 4 * n;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int64_t p = tb0 + (int64_t)t * NT + tid;
+        if (p < n) {
+            pc[p] = G * ox[t];
+            pc[n + p] = G * oy[t];
+            pc[2 * n + p] = G * oz[t];
+            pc[3 * n + p] = -G * og[t];
+        }
+    }
+}
+
+constexpr int kBlock = 256;
+
+__global__ __launch_bounds__(kBlock) void k_vjp_reduce(const double* __restrict__ part,
+                                                       int chunks, int64_t n,
+                                                       double* __restrict__ lam_r,
+                                                       double* __restrict__ g_m)
+{
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n) return;
+    for (int k = 0; k < 4; ++k) {
+        double a = 0.0;
+        for (int c = 0; c < chunks; ++c) a += part[(int64_t)c * 4 * n + (int64_t)k * n + q];
+        if (k < 3) lam_r[(int64_t)k * n + q] += a;
+        else       g_m[q] += a;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale(const double* __restrict__ x, double c,
+                                                  int64_t m, double* __restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < m) y[i] = c * x[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_axpy(const double* __restrict__ x, double c,
+                                                 int64_t m, double* __restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < m) y[i] = __builtin_fma(c, x[i], y[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(double* __restrict__ y, double v, int64_t m)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < m) y[i] = v;
+}
+
+}  // namespace
+
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <int T, int W>
+static hipError_t vjp_tw(const double* pos, const double* mass, const double* u, int64_t n,
+                         int64_t L, int chunks, double G, double* part, hipStream_t s)
+{
+    constexpr int NT = 64 * W;
+    const dim3 grid((unsigned)((n + (int64_t)NT * T - 1) / ((int64_t)NT * T)), (unsigned)chunks);
+    hipLaunchKernelGGL((k_vjp<T, W>), grid, dim3(NT), 0, s, pos, mass, u, n, L, G, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp(const Tile& tile, const double* pos, const double* mass, const double* u,
+                      int64_t n, double G, double* part, hipStream_t s)
+{
+    const int64_t L = chunk_length(n, tile);
+    const int chunks = (int)((n + L - 1) / L);
+#define NB_CASE(TT, WW) \
+    if (tile.tpl == TT && tile.waves == WW) return vjp_tw<TT, WW>(pos, mass, u, n, L, chunks, G, part, s);
+    NB_CASE(1, 1) NB_CASE(1, 2) NB_CASE(1, 4) NB_CASE(2, 1) NB_CASE(2, 2) NB_CASE(2, 4)
+#undef NB_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_vjp_reduce(const double* part, int chunks, int64_t n, double* lam_r,
+                             double* g_m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_vjp_reduce, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, part,
+                       chunks, n, lam_r, g_m);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(const double* x, double c, int64_t m, double* y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale, dim3(blocks_for(m, kBlock)), dim3(kBlock), 0, s, x, c, m, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(const double* x, double c, int64_t m, double* y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axpy, dim3(blocks_for(m, kBlock)), dim3(kBlock), 0, s, x, c, m, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double* y, double v, int64_t m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(m, kBlock)), dim3(kBlock), 0, s, y, v, m);
+    return hipGetLastError();
+}
+
+}  // namespace nb

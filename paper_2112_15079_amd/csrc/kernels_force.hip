@@ -1,0 +1,389 @@
+// Force pass of Eq. (1): a_p = sum_{j != p} G m_j (r_j - r_p) / |r_j - r_p|^3.
+//
+// gfx950 design (vector ALU bound, no MFMA: the pair sum is not a dense
+// contraction):
+//  * positions and masses are structure-of-arrays planes, so the per-target
+//    and per-source loads are unit-stride;
+//  * a workgroup stages one tile of 64*waves sources in LDS as packed
+//    (x, y, z, G m) doubles; every lane of a wavefront reads the same source,
+//    so each LDS read is a broadcast;
+//  * each lane keeps `tpl` targets and their accumulators in registers, so one
+//    LDS read feeds tpl pair evaluations;
+//  * the source range is split into chunks (grid.y) to give small systems
+//    enough workgroups for 256 CUs; chunk partials are summed in a fixed
+//    order by the step epilogue, so results are deterministic;
+//  * the self pair is masked only in the tiles that overlap the workgroup's
+//    own targets.
+#include "common.hpp"
+
+namespace nb {
+namespace {
+
+struct __attribute__((aligned(32))) Src {
+    double x, y, z, gm;
+};
+
+// Padding source for the ragged last tile: massless and far away, so its
+// term is an exact zero without a branch.
+constexpr double kPad = 1.0e18;
+
+// G m r^-3 to full FP64 accuracy.  The FP32 hardware reciprocal square root
+// y0 (relative error below 2^-22) is exact in FP64 and so is y0^2, hence
+// e = 1 - r2 y0^2 is formed with a single rounding; then
+//   r^-3 = y0^3 (1 - e)^(-3/2) = y0^3 (1 + 3/2 e + 15/8 e^2 + O(e^3)),
+// and the dropped e^3 term is below 1e-18 relative.
+// c.a = 15/8 and c.b = 3/2 live in vector registers (see vreg_const) so that
+// the polynomial is a single v_fma_f64.
+struct PolyConst {
+    double a, b;
+};
+
+__device__ __forceinline__ double gm_rinv3_f64(double r2, double gm, const PolyConst& c)
+{
+    const double y = (double)__builtin_amdgcn_rsqf((float)r2);
+    const double y2 = y * y;
+    const double e = __builtin_fma(-r2, y2, 1.0);
+    const double g = gm * (y2 * y);
+    const double q = e * __builtin_fma(e, c.a, c.b);
+    return __builtin_fma(g, q, g);
+}
+
+// A loop-invariant constant kept in a vector register: gfx9 VOP3 encodings
+// take no literal operand and at most one scalar register, so a polynomial
+// with two non-inline constants otherwise costs two extra moves per use.
+__device__ __forceinline__ double vreg_const(double c)
+{
+    asm volatile("" : "+v"(c));
+    return c;
+}
+
+// G m r^-3 with one Newton step on the FP32 reciprocal square root:
+// y1 = y0 (1 + e/2), e = 1 - r2 y0^2, relative error about 3/2 e^2 (<= 3e-13).
+__device__ __forceinline__ double gm_rinv3_newton1(double r2, double gm)
+{
+    const double y = (double)__builtin_amdgcn_rsqf((float)r2);
+    const double e = __builtin_fma(-r2, y * y, 1.0);
+    const double y1 = __builtin_fma(0.5 * y, e, y);
+    return gm * (y1 * y1 * y1);
+}
+
+template <int T>
+struct Targets {
+    double x[T], y[T], z[T];
+    int id[T];
+};
+
+// `pos` points at the system's first body; planes are `stride` apart.
+template <int T, int NT>
+__device__ __forceinline__ void load_targets(Targets<T>& tg, const double* __restrict__ pos,
+                                             int64_t stride, int64_t n, int64_t base, int tid)
+{
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int64_t p = base + (int64_t)t * NT + tid;
+        const int64_t q = p < n ? p : n - 1;
+        tg.id[t] = (int)p;
+        tg.x[t] = pos[q];
+        tg.y[t] = pos[stride + q];
+        tg.z[t] = pos[2 * stride + q];
+    }
+}
+
+__device__ __forceinline__ Src load_source(const double* __restrict__ pos,
+                                           const double* __restrict__ mass, int64_t stride,
+                                           int64_t j, int64_t jend, double G)
+{
+    Src s;
+    if (j < jend) {
+        s.x = pos[j];
+        s.y = pos[stride + j];
+        s.z = pos[2 * stride + j];
+        s.gm = G * mass[j];
+    } else {
+        s.x = kPad;
+        s.y = kPad;
+        s.z = kPad;
+        s.gm = 0.0;
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 sweep over sources [jb, je) of the LDS tile.
+template <int T, bool MASK, bool NEWTON1>
+__device__ __forceinline__ void sweep_f64(const Src* __restrict__ tile, int jb, int je, int j0,
+                                          const Targets<T>& tg, double (&ax)[T], double (&ay)[T],
+                                          double (&az)[T], const PolyConst& c32)
+{
+#pragma unroll 4
+    for (int jj = jb; jj < je; ++jj) {
+        const Src s = tile[jj];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const double dx = s.x - tg.x[t];
+            const double dy = s.y - tg.y[t];
+            const double dz = s.z - tg.z[t];
+            const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+            double f = NEWTON1 ? gm_rinv3_newton1(r2, s.gm) : gm_rinv3_f64(r2, s.gm, c32);
+            if (MASK) f = (j0 + jj == tg.id[t]) ? 0.0 : f;
+            ax[t] = __builtin_fma(f, dx, ax[t]);
+            ay[t] = __builtin_fma(f, dy, ay[t]);
+            az[t] = __builtin_fma(f, dz, az[t]);
+        }
+    }
+}
+
+// FP32 sweep for light sources: FP64 displacement, then the term in FP32;
+// the terms of each block of kBlk sources are added in FP32 and each block
+// sum enters a Kahan-compensated FP32 running sum.
+constexpr int kBlk = 16;
+
+template <int T>
+struct Kahan {
+    float sx[T], sy[T], sz[T], cx[T], cy[T], cz[T];
+};
+
+__device__ __forceinline__ void kahan_add(float& s, float& c, float x)
+{
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+template <int T, bool MASK>
+__device__ __forceinline__ void sweep_small(const Src* __restrict__ tile, int jb, int je, int j0,
+                                            const Targets<T>& tg, Kahan<T>& k)
+{
+    for (int b0 = jb; b0 < je; b0 += kBlk) {
+        const int b1 = (b0 + kBlk < je) ? b0 + kBlk : je;
+        float bx[T], by[T], bz[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) { bx[t] = 0.f; by[t] = 0.f; bz[t] = 0.f; }
+#pragma unroll 4
+        for (int jj = b0; jj < b1; ++jj) {
+            const Src s = tile[jj];
+            const float gm = (float)s.gm;
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const float dx = (float)(s.x - tg.x[t]);
+                const float dy = (float)(s.y - tg.y[t]);
+                const float dz = (float)(s.z - tg.z[t]);
+                const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+                const float y = __builtin_amdgcn_rsqf(r2);
+                float w = gm * (y * y * y);
+                if (MASK) w = (j0 + jj == tg.id[t]) ? 0.f : w;
+                bx[t] = __builtin_fmaf(w, dx, bx[t]);
+                by[t] = __builtin_fmaf(w, dy, by[t]);
+                bz[t] = __builtin_fmaf(w, dz, bz[t]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            kahan_add(k.sx[t], k.cx[t], bx[t]);
+            kahan_add(k.sy[t], k.cy[t], by[t]);
+            kahan_add(k.sz[t], k.cz[t], bz[t]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One workgroup: targets [tb0, tb0 + NT*T), sources [jbeg, jend) of a system
+// of n bodies whose planes start at pos/mass/part_c and are `stride` apart.
+template <int T, int W, bool SPLIT>
+__device__ __forceinline__ void force_block(const double* __restrict__ pos,
+                                            const double* __restrict__ mass, int64_t stride,
+                                            int64_t n, int64_t n_major, double G, int64_t tb0,
+                                            int64_t jbeg, int64_t jend,
+                                            double* __restrict__ part_c)
+{
+    constexpr int NT = 64 * W;
+    __shared__ Src tile[NT];
+    const int tid = threadIdx.x;
+
+    Targets<T> tg;
+    load_targets<T, NT>(tg, pos, stride, n, tb0, tid);
+    double ax[T], ay[T], az[T];
+    Kahan<T> k;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        ax[t] = 0.0; ay[t] = 0.0; az[t] = 0.0;
+        k.sx[t] = 0.f; k.sy[t] = 0.f; k.sz[t] = 0.f;
+        k.cx[t] = 0.f; k.cy[t] = 0.f; k.cz[t] = 0.f;
+    }
+    const int64_t tend = tb0 + (int64_t)NT * T;
+    const PolyConst c32 = {vreg_const(1.875), vreg_const(1.5)};
+
+    Src next = load_source(pos, mass, stride, jbeg + tid, jend, G);
+    for (int64_t j0 = jbeg; j0 < jend; j0 += NT) {
+        __syncthreads();
+        tile[tid] = next;
+        __syncthreads();
+        if (j0 + NT < jend) next = load_source(pos, mass, stride, j0 + NT + tid, jend, G);
+        const bool diag = (j0 < tend) && (tb0 < j0 + NT);
+        const int j0i = (int)j0;
+        if (!SPLIT) {
+            if (diag) sweep_f64<T, true, false>(tile, 0, NT, j0i, tg, ax, ay, az, c32);
+            else      sweep_f64<T, false, false>(tile, 0, NT, j0i, tg, ax, ay, az, c32);
+        } else {
+            int64_t jm64 = n_major - j0;
+            const int jm = jm64 <= 0 ? 0 : (jm64 >= NT ? NT : (int)jm64);
+            if (jm == NT) {
+                if (diag) sweep_f64<T, true, true>(tile, 0, NT, j0i, tg, ax, ay, az, c32);
+                else      sweep_f64<T, false, true>(tile, 0, NT, j0i, tg, ax, ay, az, c32);
+            } else if (jm == 0) {
+                if (diag) sweep_small<T, true>(tile, 0, NT, j0i, tg, k);
+                else      sweep_small<T, false>(tile, 0, NT, j0i, tg, k);
+            } else {
+                sweep_f64<T, true, true>(tile, 0, jm, j0i, tg, ax, ay, az, c32);
+                sweep_small<T, true>(tile, jm, NT, j0i, tg, k);
+            }
+        }
+    }
+
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int64_t p = tb0 + (int64_t)t * NT + tid;
+        if (p < n) {
+            double vx = ax[t], vy = ay[t], vz = az[t];
+            if (SPLIT) {
+                vx += (double)k.sx[t] - (double)k.cx[t];
+                vy += (double)k.sy[t] - (double)k.cy[t];
+                vz += (double)k.sz[t] - (double)k.cz[t];
+            }
+            part_c[p] = vx;
+            part_c[stride + p] = vy;
+            part_c[2 * stride + p] = vz;
+        }
+    }
+}
+
+template <int T, int W, bool SPLIT>
+__global__ __launch_bounds__(64 * W) void k_force(const double* __restrict__ pos,
+                                                  const double* __restrict__ mass, int64_t n,
+                                                  const int64_t* __restrict__ nmaj,
+                                                  int64_t chunk_len, double G,
+                                                  double* __restrict__ part)
+{
+    constexpr int NT = 64 * W;
+    const int64_t n_major = SPLIT ? nmaj[0] : 0;
+    const int64_t tb0 = (int64_t)blockIdx.x * NT * T;
+    const int64_t c = blockIdx.y;
+    const int64_t jbeg = c * chunk_len;
+    const int64_t jend = (jbeg + chunk_len < n) ? jbeg + chunk_len : n;
+    force_block<T, W, SPLIT>(pos, mass, n, n, n_major, G, tb0, jbeg, jend, part + c * 3 * n);
+}
+
+// Batched: a persistent grid walks a list of work units (system, target
+// block, chunk), sorted by decreasing cost on the host.  Systems are
+// contiguous sub-ranges of the concatenated planes (stride n_total).
+template <int T, int W, bool SPLIT>
+__global__ __launch_bounds__(64 * W) void k_force_batched(const double* __restrict__ pos,
+                                                          const double* __restrict__ mass,
+                                                          int64_t n_total, double G,
+                                                          const BatchUnit* __restrict__ units,
+                                                          int64_t num_units,
+                                                          const int64_t* __restrict__ nmaj,
+                                                          double* __restrict__ part)
+{
+    constexpr int NT = 64 * W;
+    for (int64_t u = blockIdx.x; u < num_units; u += gridDim.x) {
+        const BatchUnit w = units[u];
+        const int64_t n_major = SPLIT ? nmaj[w.sys] : 0;
+        const int64_t n = w.n;
+        const int64_t chunk_len = ((n + w.chunks - 1) / w.chunks + NT - 1) / NT * NT;
+        const int64_t jbeg = (int64_t)w.chunk * chunk_len;
+        const int64_t jend = (jbeg + chunk_len < n) ? jbeg + chunk_len : n;
+        const int64_t tb0 = (int64_t)w.tblock * NT * T;
+        force_block<T, W, SPLIT>(pos + w.body0, mass + w.body0, n_total, n, n_major, G, tb0,
+                                 jbeg, jend, part + (int64_t)w.chunk * 3 * n_total + w.body0);
+        __syncthreads();   // the LDS tile is reused by the next unit
+    }
+}
+
+
+}  // namespace
+
+bool tile_supported(const Tile& t)
+{
+    const bool tpl_ok = t.tpl == 1 || t.tpl == 2 || t.tpl == 4;
+    const bool w_ok = t.waves == 1 || t.waves == 2 || t.waves == 4 || t.waves == 8;
+    return tpl_ok && w_ok && t.chunks >= 1 && t.chunks <= kMaxChunks;
+}
+
+int64_t chunk_length(int64_t n, const Tile& t)
+{
+    const int64_t tw = tile_width(t);
+    const int64_t per = (n + t.chunks - 1) / t.chunks;
+    return (per + tw - 1) / tw * tw;
+}
+
+template <int T, int W>
+static hipError_t launch_tw(int precision, const double* pos, const double* mass, int64_t n,
+                            const int64_t* nmaj, double G, int64_t chunk_len, int chunks,
+                            double* part, hipStream_t s)
+{
+    constexpr int NT = 64 * W;
+    const dim3 grid((unsigned)((n + (int64_t)NT * T - 1) / ((int64_t)NT * T)), (unsigned)chunks);
+    if (precision == 0)
+        hipLaunchKernelGGL((k_force<T, W, false>), grid, dim3(NT), 0, s, pos, mass, n, nmaj,
+                           chunk_len, G, part);
+    else
+        hipLaunchKernelGGL((k_force<T, W, true>), grid, dim3(NT), 0, s, pos, mass, n, nmaj,
+                           chunk_len, G, part);
+    return hipGetLastError();
+}
+
+template <int T, int W>
+static hipError_t launch_batched_tw(int precision, const double* pos, const double* mass,
+                                    int64_t n_total, double G, const BatchUnit* units,
+                                    int64_t num_units, const int64_t* nmaj, int grid,
+                                    double* part, hipStream_t s)
+{
+    constexpr int NT = 64 * W;
+    if (precision == 0)
+        hipLaunchKernelGGL((k_force_batched<T, W, false>), dim3(grid), dim3(NT), 0, s, pos, mass,
+                           n_total, G, units, num_units, nmaj, part);
+    else
+        hipLaunchKernelGGL((k_force_batched<T, W, true>), dim3(grid), dim3(NT), 0, s, pos, mass,
+                           n_total, G, units, num_units, nmaj, part);
+    return hipGetLastError();
+}
+
+#define NB_TILE_CASES(X) \
+    X(1, 1) X(1, 2) X(1, 4) X(1, 8) X(2, 1) X(2, 2) X(2, 4) X(2, 8) X(4, 1) X(4, 2) X(4, 4) X(4, 8)
+
+int effective_chunks(int64_t n, const Tile& t)
+{
+    const int64_t L = chunk_length(n, t);
+    return (int)((n + L - 1) / L);
+}
+
+hipError_t launch_force(int precision, const Tile& tile, const double* pos, const double* mass,
+                        int64_t n, const int64_t* nmaj, double G, double* part, hipStream_t s)
+{
+    const int64_t L = chunk_length(n, tile);
+    const int chunks = effective_chunks(n, tile);
+#define NB_CASE(TT, WW)                                                                  \
+    if (tile.tpl == TT && tile.waves == WW)                                              \
+        return launch_tw<TT, WW>(precision, pos, mass, n, nmaj, G, L, chunks, part, s);
+    NB_TILE_CASES(NB_CASE)
+#undef NB_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_force_batched(int precision, const Tile& tile, const double* pos,
+                                const double* mass, int64_t n_total, double G,
+                                const BatchUnit* units, int64_t num_units, const int64_t* nmaj,
+                                int grid, double* part, hipStream_t s)
+{
+#define NB_CASE(TT, WW)                                                                   \
+    if (tile.tpl == TT && tile.waves == WW)                                               \
+        return launch_batched_tw<TT, WW>(precision, pos, mass, n_total, G, units, num_units, \
+                                         nmaj, grid, part, s);
+    NB_TILE_CASES(NB_CASE)
+#undef NB_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace nb

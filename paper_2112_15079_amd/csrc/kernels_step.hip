@@ -1,0 +1,325 @@
+// O(N) kernels around the force pass: the kick-drift-kick step epilogue that
+// realises Eqs. (3)-(4), the class-order gather/scatter of the split form,
+// and the diagnostics of Sec. 2 (energy, momenta).
+#include "common.hpp"
+
+namespace nb {
+namespace {
+
+constexpr int kBlock = 256;
+
+// Sum the chunk partials of a_p in ascending chunk order, then apply the
+// half kicks and the drift:
+//   kClose: v += dt/2 a                         (v_{i+1}, end of step i)
+//   kOpen:  v += dt/2 a;  r_out = r_in + dt v   (v_{i+3/2}, r_{i+2})
+// Eqs. (3)-(4) follow: r_{i+1} = r_i + dt (v_i + dt/2 a_i) and
+// v_{i+1} = v_i + dt/2 a_i + dt/2 a_{i+1}.
+__global__ __launch_bounds__(kBlock) void k_step(const double* __restrict__ part, int chunks,
+                                                 const int8_t* __restrict__ body_chunks,
+                                                 int64_t n, double* __restrict__ vel,
+                                                 const double* __restrict__ pos_in,
+                                                 double* __restrict__ pos_out,
+                                                 double* __restrict__ acc, double hdt, double dt,
+                                                 int mode, uint32_t* __restrict__ flags)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    const int C = body_chunks ? (int)body_chunks[p] : chunks;
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int64_t i = (int64_t)k * n + p;
+        double a = 0.0;
+        for (int c = 0; c < C; ++c) a += part[(int64_t)c * 3 * n + i];
+        finite = finite && __builtin_isfinite(a);
+        if (mode & kStoreAcc) acc[i] = a;
+        if (mode & (kClose | kOpen)) {
+            double v = vel[i];
+            if (mode & kClose) v = v + hdt * a;
+            if (mode & kOpen) {
+                v = v + hdt * a;
+                const double r = pos_in[i] + dt * v;
+                finite = finite && __builtin_isfinite(r);
+                pos_out[i] = r;
+            }
+            finite = finite && __builtin_isfinite(v);
+            vel[i] = v;
+        }
+    }
+    if (!finite && flags) atomicOr(flags, 1u);
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather(const int32_t* __restrict__ perm, int64_t n,
+                                                   const double* __restrict__ src,
+                                                   double* __restrict__ dst, int planes)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = perm[i];
+    for (int k = 0; k < planes; ++k) dst[(int64_t)k * n + i] = src[(int64_t)k * n + j];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ perm, int64_t n,
+                                                    const double* __restrict__ src,
+                                                    double* __restrict__ dst, int planes)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = perm[i];
+    for (int k = 0; k < planes; ++k) dst[(int64_t)k * n + j] = src[(int64_t)k * n + i];
+}
+
+// Stable partition of each system into mass >= thr first (one workgroup per
+// system): a count pass, then a block-wide scan per 1024-body slice.
+constexpr int kPart = 1024;
+
+__global__ __launch_bounds__(kPart) void k_partition(const double* __restrict__ mass,
+                                                     const int64_t* __restrict__ offsets,
+                                                     int64_t n_single, double thr,
+                                                     int32_t* __restrict__ perm,
+                                                     int64_t* __restrict__ nmaj)
+{
+    __shared__ int scan[kPart];
+    const int tid = threadIdx.x;
+    const int64_t b0 = offsets ? offsets[blockIdx.x] : 0;
+    const int64_t b1 = offsets ? offsets[blockIdx.x + 1] : n_single;
+
+    int cnt = 0;
+    for (int64_t i = b0 + tid; i < b1; i += kPart) cnt += (mass[i] >= thr) ? 1 : 0;
+    scan[tid] = cnt;
+    __syncthreads();
+    for (int w = kPart / 2; w > 0; w >>= 1) {
+        if (tid < w) scan[tid] += scan[tid + w];
+        __syncthreads();
+    }
+    const int64_t total = scan[0];
+    __syncthreads();
+
+    int64_t base_major = 0, base_small = total;
+    for (int64_t c0 = b0; c0 < b1; c0 += kPart) {
+        const int64_t i = c0 + tid;
+        const bool valid = i < b1;
+        const int f = (valid && mass[i] >= thr) ? 1 : 0;
+        scan[tid] = f;
+        __syncthreads();
+        for (int off = 1; off < kPart; off <<= 1) {
+            const int v = tid >= off ? scan[tid - off] : 0;
+            __syncthreads();
+            scan[tid] += v;
+            __syncthreads();
+        }
+        const int excl = scan[tid] - f;          // majors before tid in this slice
+        const int chunk_major = scan[kPart - 1];
+        if (valid) {
+            if (f) perm[b0 + base_major + excl] = (int32_t)i;
+            else   perm[b0 + base_small + (tid - excl)] = (int32_t)i;
+        }
+        const int64_t nvalid = (b1 - c0 < kPart) ? (b1 - c0) : kPart;
+        base_major += chunk_major;
+        base_small += nvalid - chunk_major;
+        __syncthreads();
+    }
+    if (tid == 0) nmaj[blockIdx.x] = total;
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics.  Neumaier-compensated sums; fixed summation order.
+struct CSum {
+    double s, c;
+};
+
+__device__ __forceinline__ void cadd(CSum& a, double x)
+{
+    const double t = a.s + x;
+    if (fabs(a.s) >= fabs(x)) a.c += (a.s - t) + x;
+    else                      a.c += (x - t) + a.s;
+    a.s = t;
+}
+
+__device__ __forceinline__ void cmerge(CSum& a, const CSum& b)
+{
+    cadd(a, b.s);
+    cadd(a, b.c);
+}
+
+// 1/r to full FP64 accuracy: y0 from the FP32 hardware reciprocal square root,
+// e = 1 - r2 y0^2 (one rounding), 1/r = y0 (1 + e/2 + 3/8 e^2 + O(e^3)).
+__device__ __forceinline__ double rinv_f64(double r2)
+{
+    const double y = (double)__builtin_amdgcn_rsqf((float)r2);
+    const double e = __builtin_fma(-r2, y * y, 1.0);
+    return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
+}
+
+constexpr int kRowTile = 256;
+
+// rows[p] = -G m_p / 2 * sum_{j != p} m_j / |r_j - r_p|; sum_p rows[p] is the
+// pair potential of Sec. 2 (each pair counted twice, hence the half).
+__global__ __launch_bounds__(kRowTile) void k_potential_rows(const double* __restrict__ pos,
+                                                             const double* __restrict__ mass,
+                                                             int64_t n, double G,
+                                                             double* __restrict__ rows)
+{
+    __shared__ double sx[kRowTile], sy[kRowTile], sz[kRowTile], sm[kRowTile];
+    const int tid = threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * kRowTile + tid;
+    const int64_t q = p < n ? p : n - 1;
+    const double px = pos[q], py = pos[n + q], pz = pos[2 * n + q];
+    CSum acc = {0.0, 0.0};
+    for (int64_t j0 = 0; j0 < n; j0 += kRowTile) {
+        const int64_t j = j0 + tid;
+        __syncthreads();
+        if (j < n) {
+            sx[tid] = pos[j];
+            sy[tid] = pos[n + j];
+            sz[tid] = pos[2 * n + j];
+            sm[tid] = mass[j];
+        }
+        __syncthreads();
+        const int cnt = (n - j0 < kRowTile) ? (int)(n - j0) : kRowTile;
+        for (int jj = 0; jj < cnt; ++jj) {
+            if (j0 + jj == q) continue;
+            const double dx = sx[jj] - px, dy = sy[jj] - py, dz = sz[jj] - pz;
+            const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+            cadd(acc, sm[jj] * rinv_f64(r2));
+        }
+    }
+    if (p < n) rows[p] = -0.5 * G * mass[p] * (acc.s + acc.c);
+}
+
+constexpr int kRed = 1024;
+
+__device__ void block_reduce(CSum* sh, CSum v, int nvals)
+{
+    // Writes the combined value of all threads' v into sh[0]; fixed order.
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int w = kRed / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            CSum a = sh[tid];
+            cmerge(a, sh[tid + w]);
+            sh[tid] = a;
+        }
+        __syncthreads();
+    }
+    (void)nvals;
+}
+
+__global__ __launch_bounds__(kRed) void k_energy_finish(const double* __restrict__ rows,
+                                                        const double* __restrict__ vel,
+                                                        const double* __restrict__ mass,
+                                                        int64_t n, double* __restrict__ out)
+{
+    __shared__ CSum sh[kRed];
+    const int tid = threadIdx.x;
+    CSum kin = {0.0, 0.0}, pot = {0.0, 0.0};
+    for (int64_t i = tid; i < n; i += kRed) {
+        const double vx = vel[i], vy = vel[n + i], vz = vel[2 * n + i];
+        cadd(kin, 0.5 * mass[i] * (vx * vx + vy * vy + vz * vz));
+        cadd(pot, rows[i]);
+    }
+    block_reduce(sh, kin, kRed);
+    const CSum K = sh[0];
+    __syncthreads();
+    block_reduce(sh, pot, kRed);
+    const CSum U = sh[0];
+    if (tid == 0) {
+        const double k = K.s + K.c, u = U.s + U.c;
+        CSum e = {0.0, 0.0};
+        cadd(e, k);
+        cadd(e, u);
+        out[0] = k;
+        out[1] = u;
+        out[2] = e.s + e.c;
+    }
+}
+
+__global__ __launch_bounds__(kRed) void k_momenta(const double* __restrict__ pos,
+                                                  const double* __restrict__ vel,
+                                                  const double* __restrict__ mass, int64_t n,
+                                                  double* __restrict__ out)
+{
+    __shared__ CSum sh[kRed];
+    const int tid = threadIdx.x;
+    CSum c[6];
+    for (int k = 0; k < 6; ++k) c[k] = {0.0, 0.0};
+    for (int64_t i = tid; i < n; i += kRed) {
+        const double rx = pos[i], ry = pos[n + i], rz = pos[2 * n + i];
+        const double vx = vel[i], vy = vel[n + i], vz = vel[2 * n + i];
+        const double m = mass[i];
+        cadd(c[0], m * vx);
+        cadd(c[1], m * vy);
+        cadd(c[2], m * vz);
+        cadd(c[3], m * (ry * vz - rz * vy));
+        cadd(c[4], m * (rz * vx - rx * vz));
+        cadd(c[5], m * (rx * vy - ry * vx));
+    }
+    for (int k = 0; k < 6; ++k) {
+        block_reduce(sh, c[k], kRed);
+        if (tid == 0) out[k] = sh[0].s + sh[0].c;
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_step(const double* part, int chunks, const int8_t* body_chunks, int64_t n,
+                       double* vel, const double* pos_in, double* pos_out, double* acc,
+                       double dt, int mode, uint32_t* flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_step, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, part, chunks,
+                       body_chunks, n, vel, pos_in, pos_out, acc, 0.5 * dt, dt, mode, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_partition(const double* mass, const int64_t* offsets, int num_systems,
+                            int64_t n_single, double threshold, int32_t* perm, int64_t* nmaj,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_partition, dim3((unsigned)num_systems), dim3(kPart), 0, s, mass, offsets,
+                       n_single, threshold, perm, nmaj);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const int32_t* perm, int64_t n, const double* src, double* dst,
+                         int planes, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, perm, n, src,
+                       dst, planes);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const int32_t* perm, int64_t n, const double* src, double* dst,
+                          int planes, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, perm, n, src,
+                       dst, planes);
+    return hipGetLastError();
+}
+
+hipError_t launch_potential_rows(const double* pos, const double* mass, int64_t n, double G,
+                                 double* rows, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_potential_rows, dim3(blocks_for(n, kRowTile)), dim3(kRowTile), 0, s,
+                       pos, mass, n, G, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_finish(const double* rows, const double* vel, const double* mass,
+                                int64_t n, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_energy_finish, dim3(1), dim3(kRed), 0, s, rows, vel, mass, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_momenta(const double* pos, const double* vel, const double* mass, int64_t n,
+                          double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_momenta, dim3(1), dim3(kRed), 0, s, pos, vel, mass, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace nb

@@ -1,0 +1,248 @@
+"""Python entry points with the names of the C ABI (include/nbody.h).
+
+All state is float64 torch tensors on the GPU in structure-of-arrays form:
+``pos`` and ``vel`` of shape (3, n), ``mass`` of shape (n,).  Work is
+enqueued on the current torch stream.  Each function only checks and
+marshals arguments; the computation happens in libnbody.so.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _capi as C
+from ._capi import NBODY_FP64, NBODY_SPLIT
+
+_PREC = {"fp64": NBODY_FP64, "split": NBODY_SPLIT, NBODY_FP64: NBODY_FP64, NBODY_SPLIT: NBODY_SPLIT}
+
+#: 3e17 kg in solar masses (1 Msun = 1.98847e30 kg): the small-body class
+#: boundary for the split form in AU / day / Msun units.
+SMALL_MASS_MSUN = 3e17 / 1.98847e30
+
+
+def _prec(p) -> int:
+    try:
+        return _PREC[p]
+    except KeyError:
+        raise ValueError(f"precision must be 'fp64' or 'split', got {p!r}") from None
+
+
+def _state(t: torch.Tensor, name: str, n: int | None = None, planes: int = 3) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU (no CPU path exists)")
+    want = (planes, n) if planes > 1 else (n,)
+    if n is not None and tuple(t.shape) != want:
+        raise ValueError(f"{name} must have shape {want}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _mass(mass: torch.Tensor) -> int:
+    _state(mass, "mass", planes=1)
+    if mass.dim() != 1 or mass.shape[0] < 1:
+        raise ValueError("mass must be a non-empty 1-D tensor")
+    return int(mass.shape[0])
+
+
+def _same_device(*ts):
+    d = ts[0].device
+    for t in ts[1:]:
+        if t.device != d:
+            raise ValueError("all tensors must be on one device")
+    return d
+
+
+def _small(precision: int, small_mass):
+    if precision == NBODY_SPLIT:
+        return float(SMALL_MASS_MSUN if small_mass is None else small_mass)
+    return 0.0
+
+
+def accel(pos, mass, G, precision="fp64", small_mass=None, out=None):
+    """Eq. (1) accelerations at ``pos``; returns a (3, n) tensor."""
+    n = _mass(mass)
+    _state(pos, "pos", n)
+    dev = _same_device(pos, mass)
+    p = _prec(precision)
+    if out is None:
+        out = torch.empty((3, n), dtype=torch.float64, device=dev)
+    _state(out, "out", n)
+    lib = C.load()
+    nb = C.workspace_bytes(C.OP_ACCEL, n, precision=p)
+    ws = C.workspace(nb, dev)
+    st = lib.nbody_accel(pos.data_ptr(), None, mass.data_ptr(), n, float(G), 0.0, 0,
+                         out.data_ptr(), p, _small(p, small_mass), ws.data_ptr(), ws.numel(),
+                         C.stream_handle(dev))
+    C.check(st, "nbody_accel")
+    return out
+
+
+def verlet_run(pos, vel, mass, G, dt, steps, precision="fp64", small_mass=None):
+    """Advances (pos, vel) in place by ``steps`` velocity-Verlet steps
+    (Eqs. (3)-(4)); returns (pos, vel)."""
+    n = _mass(mass)
+    _state(pos, "pos", n)
+    _state(vel, "vel", n)
+    dev = _same_device(pos, vel, mass)
+    p = _prec(precision)
+    steps = int(steps)
+    lib = C.load()
+    nb = C.workspace_bytes(C.OP_RUN, n, steps=steps, precision=p)
+    ws = C.workspace(nb, dev)
+    st = lib.nbody_verlet_run(pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), n, float(G),
+                              float(dt), steps, p, _small(p, small_mass), ws.data_ptr(),
+                              ws.numel(), C.stream_handle(dev))
+    C.check(st, "nbody_verlet_run")
+    return pos, vel
+
+
+def verlet_adjoint(pos0, vel0, mass, G, dt, steps, checkpoint_every, grad_posT, grad_velT):
+    """Discrete adjoint of an FP64 run: returns (dL/dr0, dL/dv0, dL/dm, r_T, v_T)
+    given dL/dr_T and dL/dv_T."""
+    n = _mass(mass)
+    for t, name in ((pos0, "pos0"), (vel0, "vel0"), (grad_posT, "grad_posT"),
+                    (grad_velT, "grad_velT")):
+        _state(t, name, n)
+    dev = _same_device(pos0, vel0, mass, grad_posT, grad_velT)
+    steps = int(steps)
+    K = int(checkpoint_every)
+    gr = torch.empty((3, n), dtype=torch.float64, device=dev)
+    gv = torch.empty_like(gr)
+    gm = torch.empty((n,), dtype=torch.float64, device=dev)
+    pT = torch.empty_like(gr)
+    vT = torch.empty_like(gr)
+    lib = C.load()
+    nb = C.workspace_bytes(C.OP_ADJOINT, n, steps=steps, checkpoint_every=max(K, 1))
+    ws = C.workspace(nb, dev)
+    st = lib.nbody_verlet_adjoint(pos0.data_ptr(), vel0.data_ptr(), mass.data_ptr(), n, float(G),
+                                  float(dt), steps, K, grad_posT.data_ptr(), grad_velT.data_ptr(),
+                                  gr.data_ptr(), gv.data_ptr(), gm.data_ptr(), pT.data_ptr(),
+                                  vT.data_ptr(), ws.data_ptr(), ws.numel(), C.stream_handle(dev))
+    C.check(st, "nbody_verlet_adjoint")
+    return gr, gv, gm, pT, vT
+
+
+def verlet_run_batched(pos, vel, mass, offsets, G, dt, steps, precision="fp64", small_mass=None):
+    """Advances many independent systems (concatenated SoA, system k owns
+    bodies offsets[k]:offsets[k+1]) in place."""
+    n = _mass(mass)
+    _state(pos, "pos", n)
+    _state(vel, "vel", n)
+    dev = _same_device(pos, vel, mass)
+    offs = [int(x) for x in offsets]
+    ns = len(offs) - 1
+    if ns < 1 or offs[-1] != n:
+        raise ValueError("offsets must have num_systems+1 entries ending at n")
+    p = _prec(precision)
+    arr = (ctypes.c_int64 * len(offs))(*offs)
+    lib = C.load()
+    nb = C.workspace_bytes(C.OP_BATCHED, n, num_systems=ns, steps=int(steps), precision=p)
+    ws = C.workspace(nb, dev)
+    st = lib.nbody_verlet_run_batched(pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), arr, ns,
+                                      float(G), float(dt), int(steps), p, _small(p, small_mass),
+                                      ws.data_ptr(), ws.numel(), C.stream_handle(dev))
+    C.check(st, "nbody_verlet_run_batched")
+    return pos, vel
+
+
+def energy(pos, vel, mass, G):
+    """(kinetic, potential, total) as a device tensor of 3 doubles."""
+    n = _mass(mass)
+    _state(pos, "pos", n)
+    _state(vel, "vel", n)
+    dev = _same_device(pos, vel, mass)
+    out = torch.empty(3, dtype=torch.float64, device=dev)
+    lib = C.load()
+    nb = C.workspace_bytes(C.OP_ENERGY, n)
+    ws = C.workspace(nb, dev)
+    st = lib.nbody_energy(pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), n, float(G),
+                          out.data_ptr(), ws.data_ptr(), ws.numel(), C.stream_handle(dev))
+    C.check(st, "nbody_energy")
+    return out
+
+
+def momenta(pos, vel, mass):
+    """(Px, Py, Pz, Lx, Ly, Lz) as a device tensor of 6 doubles."""
+    n = _mass(mass)
+    _state(pos, "pos", n)
+    _state(vel, "vel", n)
+    dev = _same_device(pos, vel, mass)
+    out = torch.empty(6, dtype=torch.float64, device=dev)
+    st = C.load().nbody_momenta(pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), n,
+                                out.data_ptr(), C.stream_handle(dev))
+    C.check(st, "nbody_momenta")
+    return out
+
+
+def get_flags(device=None, clear=False) -> int:
+    """Flags of the last runs on this device's shared workspace (bit 0:
+    non-finite value produced).  Synchronises the current stream."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    ws = C.workspace(256, dev)
+    v = ctypes.c_int32(0)
+    st = C.load().nbody_get_flags(ws.data_ptr(), C.stream_handle(dev), int(bool(clear)),
+                                  ctypes.byref(v))
+    C.check(st, "nbody_get_flags")
+    return int(v.value)
+
+
+def get_tile(kind, precision, n):
+    t = C.Tile()
+    C.check(C.load().nbody_get_tile(int(kind), _prec(precision), int(n), ctypes.byref(t)),
+            "nbody_get_tile")
+    return t.as_dict()
+
+
+def set_tile(kind, precision, n, targets_per_lane, waves, chunks):
+    t = C.Tile(int(targets_per_lane), int(waves), int(chunks))
+    C.check(C.load().nbody_set_tile(int(kind), _prec(precision), int(n), ctypes.byref(t)),
+            "nbody_set_tile")
+
+
+def autotune(pos, mass, G, precision="fp64", kind=0, small_mass=None):
+    """Times candidate tile shapes on this data, keeps the fastest for n's
+    size class; returns (tile dict, ms per pass)."""
+    n = _mass(mass)
+    _state(pos, "pos", n)
+    dev = _same_device(pos, mass)
+    p = _prec(precision)
+    op = C.OP_ACCEL if kind == 0 else C.OP_ADJOINT
+    nb = C.workspace_bytes(op, n, steps=1, precision=p)
+    ws = C.workspace(nb, dev)
+    t = C.Tile()
+    ms = ctypes.c_double(0)
+    st = C.load().nbody_autotune(int(kind), p, pos.data_ptr(), mass.data_ptr(), n, float(G),
+                                 _small(p, small_mass), ws.data_ptr(), ws.numel(),
+                                 C.stream_handle(dev), ctypes.byref(t), ctypes.byref(ms))
+    C.check(st, "nbody_autotune")
+    return t.as_dict(), float(ms.value)
+
+
+def time_force(pos, mass, G, precision="fp64", kind=0, reps=50, small_mass=None):
+    """Average ms of one force pass (HIP events on the current stream)."""
+    n = _mass(mass)
+    _state(pos, "pos", n)
+    dev = _same_device(pos, mass)
+    p = _prec(precision)
+    op = C.OP_ACCEL if kind == 0 else C.OP_ADJOINT
+    ws = C.workspace(C.workspace_bytes(op, n, steps=1, precision=p), dev)
+    ms = ctypes.c_double(0)
+    st = C.load().nbody_time_force(int(kind), p, pos.data_ptr(), mass.data_ptr(), n, float(G),
+                                   _small(p, small_mass), int(reps), ws.data_ptr(), ws.numel(),
+                                   C.stream_handle(dev), ctypes.byref(ms))
+    C.check(st, "nbody_time_force")
+    return float(ms.value)
+
+
+def reset_caches():
+    C.load().nbody_reset_caches()
+
+
+def version() -> str:
+    return C.load().nbody_version().decode()

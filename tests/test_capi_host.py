@@ -1,0 +1,153 @@
+"""The C-ABI library on the host: it loads, exports every symbol the header
+declares, sizes workspaces, and rejects bad arguments before any GPU work.
+No kernel is launched here (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nbody.h")
+
+C = pytest.importorskip("paper_2112_15079_amd._capi")
+
+
+def _lib():
+    if not os.path.exists(C.LIB_PATH):
+        pytest.skip("libnbody.so not built (run __graft_entry__.build())")
+    return C.load()
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nbody_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_abi():
+    names = _declared()
+    for want in ("nbody_accel", "nbody_verlet_run", "nbody_verlet_adjoint",
+                 "nbody_verlet_run_batched", "nbody_workspace_bytes", "nbody_last_error"):
+        assert want in names
+    assert set(names) == set(C.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert lib.nbody_version().decode().startswith("nbody-gfx950")
+
+
+def test_workspace_sizes():
+    lib = _lib()
+    ws = lambda *a: lib.nbody_workspace_bytes(*a)
+    a = ws(C.OP_ACCEL, 10425, 1, 0, 1, C.NBODY_FP64)
+    assert a >= 64 * 3 * 10425 * 8          # chunk partials
+    assert ws(C.OP_ACCEL, 10425, 1, 0, 1, C.NBODY_SPLIT) > a
+    assert ws(C.OP_RUN, 1, 1, 5, 1, C.NBODY_FP64) > 0
+    adj = ws(C.OP_ADJOINT, 2079, 1, 36500, 100, C.NBODY_FP64)
+    assert adj >= 366 * 6 * 2079 * 8 + 100 * 3 * 2079 * 8
+    assert ws(C.OP_BATCHED, 2_000_000, 512, 1000, 1, C.NBODY_FP64) > 0
+    # invalid requests return 0
+    assert ws(C.OP_ACCEL, 0, 1, 0, 1, C.NBODY_FP64) == 0
+    assert ws(C.OP_ADJOINT, 10, 1, 10, 0, C.NBODY_FP64) == 0
+    assert ws(9, 10, 1, 0, 1, C.NBODY_FP64) == 0
+    assert ws(C.OP_ACCEL, 10, 1, 0, 1, 7) == 0
+
+
+FAKE = ctypes.c_void_p(0x10000)   # never dereferenced: validation fails first
+
+
+def test_accel_rejects_bad_arguments():
+    lib = _lib()
+    ws = ctypes.c_void_p(0x100000)
+    big = 1 << 40
+    # null pos
+    assert lib.nbody_accel(None, None, FAKE, 10, 1.0, 0.0, 0, FAKE, 0, 0.0, ws, big, None) == C.NBODY_EINVAL
+    assert "null" in C.last_error()
+    # n < 1
+    assert lib.nbody_accel(FAKE, None, FAKE, 0, 1.0, 0.0, 0, FAKE, 0, 0.0, ws, big, None) == C.NBODY_EINVAL
+    # non-finite G
+    assert lib.nbody_accel(FAKE, None, FAKE, 5, float("nan"), 0.0, 0, FAKE, 0, 0.0, ws, big, None) == C.NBODY_EINVAL
+    # unknown precision
+    assert lib.nbody_accel(FAKE, None, FAKE, 5, 1.0, 0.0, 0, FAKE, 3, 0.0, ws, big, None) == C.NBODY_EINVAL
+    # negative split threshold
+    assert lib.nbody_accel(FAKE, None, FAKE, 5, 1.0, 0.0, 0, FAKE, 1, -1.0, ws, big, None) == C.NBODY_EINVAL
+    # null output
+    assert lib.nbody_accel(FAKE, None, FAKE, 5, 1.0, 0.0, 0, None, 0, 0.0, ws, big, None) == C.NBODY_EINVAL
+    # workspace missing / short / misaligned
+    assert lib.nbody_accel(FAKE, None, FAKE, 5, 1.0, 0.0, 0, FAKE, 0, 0.0, None, big, None) == C.NBODY_EWORKSPACE
+    assert lib.nbody_accel(FAKE, None, FAKE, 5, 1.0, 0.0, 0, FAKE, 0, 0.0, ws, 16, None) == C.NBODY_EWORKSPACE
+    assert lib.nbody_accel(FAKE, None, FAKE, 5, 1.0, 0.0, 0, FAKE, 0, 0.0,
+                           ctypes.c_void_p(0x100010), big, None) == C.NBODY_EINVAL
+    # too many bodies
+    assert lib.nbody_accel(FAKE, None, FAKE, (1 << 30) + 1, 1.0, 0.0, 0, FAKE, 0, 0.0, ws, big,
+                           None) == C.NBODY_EUNSUPPORTED
+
+
+def test_run_rejects_bad_arguments():
+    lib = _lib()
+    ws = ctypes.c_void_p(0x100000)
+    big = 1 << 40
+    assert lib.nbody_verlet_run(FAKE, None, FAKE, 5, 1.0, 0.1, 3, 0, 0.0, ws, big, None) == C.NBODY_EINVAL
+    assert lib.nbody_verlet_run(FAKE, FAKE, FAKE, 5, 1.0, 0.1, -1, 0, 0.0, ws, big, None) == C.NBODY_EINVAL
+    assert lib.nbody_verlet_run(FAKE, FAKE, FAKE, 5, 1.0, float("inf"), 3, 0, 0.0, ws, big, None) == C.NBODY_EINVAL
+    # steps = 0 is a valid no-op (returns before any launch)
+    assert lib.nbody_verlet_run(FAKE, FAKE, FAKE, 5, 1.0, 0.1, 0, 0, 0.0, ws, big, None) == C.NBODY_OK
+
+
+def test_adjoint_rejects_bad_arguments():
+    lib = _lib()
+    ws = ctypes.c_void_p(0x100000)
+    big = 1 << 40
+    args = [FAKE, FAKE, FAKE, 5, 1.0, 0.1, 10, 0, FAKE, FAKE, FAKE, FAKE, FAKE, None, None, ws, big, None]
+    assert lib.nbody_verlet_adjoint(*args) == C.NBODY_EINVAL       # checkpoint_every = 0
+    args[7] = 5
+    args[8] = None
+    assert lib.nbody_verlet_adjoint(*args) == C.NBODY_EINVAL       # null cotangent
+
+
+def test_batched_rejects_bad_offsets():
+    lib = _lib()
+    ws = ctypes.c_void_p(0x100000)
+    big = 1 << 40
+    bad = [(0, 5, 5, 9), (1, 5, 9), (0, 7, 4)]
+    for offs in bad:
+        arr = (ctypes.c_int64 * len(offs))(*offs)
+        st = lib.nbody_verlet_run_batched(FAKE, FAKE, FAKE, arr, len(offs) - 1, 1.0, 0.1, 10, 0,
+                                          0.0, ws, big, None)
+        assert st == C.NBODY_EINVAL, offs
+    assert lib.nbody_verlet_run_batched(FAKE, FAKE, FAKE, None, 1, 1.0, 0.1, 10, 0, 0.0, ws, big,
+                                        None) == C.NBODY_EINVAL
+
+
+def test_tile_table():
+    lib = _lib()
+    lib.nbody_reset_caches()
+    t = C.Tile()
+    assert lib.nbody_get_tile(0, 0, 10425, ctypes.byref(t)) == C.NBODY_OK
+    assert t.targets_per_lane in (1, 2, 4) and t.waves in (1, 2, 4, 8) and 1 <= t.chunks <= 64
+    want = C.Tile(4, 2, 7)
+    assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(want)) == C.NBODY_OK
+    assert lib.nbody_get_tile(0, 0, 10425, ctypes.byref(t)) == C.NBODY_OK
+    assert (t.targets_per_lane, t.waves, t.chunks) == (4, 2, 7)
+    assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(3, 1, 1))) == C.NBODY_EINVAL
+    assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(1, 1, 65))) == C.NBODY_EINVAL
+    assert lib.nbody_set_tile(1, 0, 100, ctypes.byref(C.Tile(4, 1, 1))) == C.NBODY_EINVAL
+    lib.nbody_reset_caches()
+
+
+def test_python_wrapper_rejects_cpu_tensors():
+    torch = pytest.importorskip("torch")
+    _lib()
+    import paper_2112_15079_amd as nb
+    pos = torch.zeros(3, 4, dtype=torch.float64)
+    mass = torch.ones(4, dtype=torch.float64)
+    with pytest.raises(ValueError, match="GPU"):
+        nb.accel(pos, mass, 1.0)
+    with pytest.raises(TypeError):
+        nb.accel(pos, mass.float(), 1.0)
+    with pytest.raises(ValueError):
+        nb.accel(pos, mass, 1.0, precision="fp16")
