@@ -50,7 +50,7 @@ def test_adjoint_zero_steps_is_identity():
     assert np.array_equal(H(Gr), lr) and np.array_equal(H(Gv), lv) and not H(Gm).any()
 
 
-def _fd_check(s, steps, K, coords, rel_tol=1e-6, floor=1e-9):
+def _fd_check(s, steps, K, coords, rel_step=1e-7, rel_tol=1e-6, floor=1e-9):
     """Central differences of L = sum_ast |r(T) - r_tgt(T)|^2 from GPU runs."""
     first = 1 + s.counts["major"]
     m = T(s.mass)
@@ -76,13 +76,13 @@ def _fd_check(s, steps, K, coords, rel_tol=1e-6, floor=1e-9):
         p0, v0, m0 = s.pos.copy(), s.vel.copy(), s.mass.copy()
         if idx < 3 * n:
             arr, flat = p0, idx
-            h = 1e-7 * max(abs(p0.ravel()[flat]), 1.0)
+            h = rel_step * max(abs(p0.ravel()[flat]), 1.0)
         elif idx < 6 * n:
             arr, flat = v0, idx - 3 * n
-            h = 1e-7 * max(abs(v0.ravel()[flat]), 0.01)
+            h = rel_step * max(abs(v0.ravel()[flat]), 0.01)
         else:
             arr, flat = m0, 1 + (idx - 6 * n)
-            h = 1e-7 * m0[flat]
+            h = rel_step * m0[flat]
         base = arr.ravel()[flat]
         arr.ravel()[flat] = base + h
         pp = final(p0, v0, m0)
@@ -113,8 +113,16 @@ def test_adjoint_vs_finite_differences_prefix():
         rng.choice(np.arange(0, 3 * 31), 2, replace=False),                # Sun/major positions
         [6 * n + int(np.argmax(s.mass[1:31]))],                            # heaviest major mass
     ]))
-    ok, adj, fds = _fd_check(s, 1000, 100, coords)
+    # At a relative step of 1e-5 the difference quotient is far above the
+    # roundoff noise of the two forward runs and its truncation error is
+    # O(h^2) ~ 1e-10: the adjoint must agree to 1e-6.
+    ok, adj, fds = _fd_check(s, 1000, 100, coords, rel_step=1e-5)
     assert ok.all()
+    # At 1e-7 the quotient carries the forward runs' roundoff (last-bit
+    # differences in every other body's trajectory, scaled by 1/h): agreement
+    # is limited by that noise, checked at a correspondingly looser level.
+    ok7, adj7, fds7 = _fd_check(s, 1000, 100, coords, rel_step=1e-7, rel_tol=1e-4)
+    assert ok7.all()
 
 
 def test_autograd_function():

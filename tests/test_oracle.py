@@ -411,3 +411,30 @@ def test_adjoint_against_finite_differences_solar():
     em[q] = hm
     fdm = (loss(s.pos, s.vel, s.mass + em) - loss(s.pos, s.vel, s.mass - em)) / (2 * hm)
     assert abs(fdm - gm[q]) <= 1e-5 * abs(fdm)
+
+
+def test_accel_against_extended_precision():
+    """Eq. (1) is an exact sum: the oracle must sit within a few ulp of it
+    even for a moon whose parent's term dominates 10^4 tiny asteroid terms.
+    The reference re-evaluates the sum in x87 80-bit extended precision."""
+    s = S.config(1)
+    if np.finfo(np.longdouble).nmant < 63:
+        pytest.skip("no extended precision long double on this platform")
+    rng = np.random.default_rng(2)
+    idx = np.unique(np.concatenate([[0, 1, 30], np.arange(31, 131), [131, 149, s.n - 1],
+                                    rng.choice(s.n, 40, replace=False)]))
+    got = oracle.accel_targets(s.pos, s.mass, s.G, idx)
+    pos = s.pos.astype(np.longdouble)
+    m = s.mass.astype(np.longdouble)
+    G = np.longdouble(s.G)
+    worst = 0.0
+    for k, p in enumerate(idx):
+        d = pos - pos[:, p:p + 1]
+        r2 = np.sum(d * d, axis=0)
+        r2[p] = 1
+        w = G * m / (r2 * np.sqrt(r2))
+        w[p] = 0
+        a = (w * d).sum(axis=1)
+        worst = max(worst, float(np.linalg.norm(got[:, k] - a.astype(np.float64))
+                                 / np.linalg.norm(a.astype(np.float64))))
+    assert worst <= 2e-15
