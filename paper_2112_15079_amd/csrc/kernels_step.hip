@@ -14,6 +14,11 @@ constexpr int kBlock = 256;
 //   kOpen:  v += dt/2 a;  r_out = r_in + dt v   (v_{i+3/2}, r_{i+2})
 // Eqs. (3)-(4) follow: r_{i+1} = r_i + dt (v_i + dt/2 a_i) and
 // v_{i+1} = v_i + dt/2 a_i + dt/2 a_{i+1}.
+// One thread per (body, component): the partial loads of a batch are issued
+// together and then added in chunk order, so the sum is the same for any
+// batch size while the loads overlap.
+constexpr int kLoadBatch = 16;
+
 __global__ __launch_bounds__(kBlock) void k_step(const double* __restrict__ part, int chunks,
                                                  const int8_t* __restrict__ body_chunks,
                                                  int64_t n, double* __restrict__ vel,
@@ -22,29 +27,34 @@ __global__ __launch_bounds__(kBlock) void k_step(const double* __restrict__ part
                                                  double* __restrict__ acc, double hdt, double dt,
                                                  int mode, uint32_t* __restrict__ flags)
 {
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= n) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;   // k * n + p
+    if (i >= 3 * n) return;
+    const int64_t p = i % n;
     const int C = body_chunks ? (int)body_chunks[p] : chunks;
-    bool finite = true;
+    const int64_t stride = 3 * n;
+    double a = 0.0;
+    for (int c0 = 0; c0 < C; c0 += kLoadBatch) {
+        double t[kLoadBatch];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int64_t i = (int64_t)k * n + p;
-        double a = 0.0;
-        for (int c = 0; c < C; ++c) a += part[(int64_t)c * 3 * n + i];
-        finite = finite && __builtin_isfinite(a);
-        if (mode & kStoreAcc) acc[i] = a;
-        if (mode & (kClose | kOpen)) {
-            double v = vel[i];
-            if (mode & kClose) v = v + hdt * a;
-            if (mode & kOpen) {
-                v = v + hdt * a;
-                const double r = pos_in[i] + dt * v;
-                finite = finite && __builtin_isfinite(r);
-                pos_out[i] = r;
-            }
-            finite = finite && __builtin_isfinite(v);
-            vel[i] = v;
+        for (int u = 0; u < kLoadBatch; ++u)
+            t[u] = (c0 + u < C) ? part[(int64_t)(c0 + u) * stride + i] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u)
+            if (c0 + u < C) a += t[u];
+    }
+    bool finite = __builtin_isfinite(a);
+    if (mode & kStoreAcc) acc[i] = a;
+    if (mode & (kClose | kOpen)) {
+        double v = vel[i];
+        if (mode & kClose) v = v + hdt * a;
+        if (mode & kOpen) {
+            v = v + hdt * a;
+            const double r = pos_in[i] + dt * v;
+            finite = finite && __builtin_isfinite(r);
+            pos_out[i] = r;
         }
+        finite = finite && __builtin_isfinite(v);
+        vel[i] = v;
     }
     if (!finite && flags) atomicOr(flags, 1u);
 }
@@ -270,7 +280,7 @@ hipError_t launch_step(const double* part, int chunks, const int8_t* body_chunks
                        double* vel, const double* pos_in, double* pos_out, double* acc,
                        double dt, int mode, uint32_t* flags, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_step, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, part, chunks,
+    hipLaunchKernelGGL(k_step, dim3(blocks_for(3 * n, kBlock)), dim3(kBlock), 0, s, part, chunks,
                        body_chunks, n, vel, pos_in, pos_out, acc, 0.5 * dt, dt, mode, flags);
     return hipGetLastError();
 }

@@ -50,8 +50,16 @@ def test_adjoint_zero_steps_is_identity():
     assert np.array_equal(H(Gr), lr) and np.array_equal(H(Gv), lv) and not H(Gm).any()
 
 
-def _fd_check(s, steps, K, coords, rel_step=1e-7, rel_tol=1e-6, floor=1e-9):
-    """Central differences of L = sum_ast |r(T) - r_tgt(T)|^2 from GPU runs."""
+def _loss_diff(pa, pb, tgt, first):
+    """L(a) - L(b) for L = sum_ast |p - tgt|^2, as sum (pa - pb)(pa + pb - 2 tgt):
+    no cancellation between two nearly equal totals."""
+    a, b = pa[:, first:], pb[:, first:]
+    return float(np.sum((a - b) * ((a - tgt[:, first:]) + (b - tgt[:, first:]))))
+
+
+def _fd_check(s, steps, K, coords, rel_step=1e-7, order=2, rel_tol=1e-6, floor=1e-9):
+    """Central differences of L = sum_ast |r(T) - r_tgt(T)|^2 from GPU runs:
+    order 2 (x +- h) or order 4 (x +- h, x +- 2h)."""
     first = 1 + s.counts["major"]
     m = T(s.mass)
     tgt0 = S.adjoint_target_perturbation(s)
@@ -84,44 +92,65 @@ def _fd_check(s, steps, K, coords, rel_step=1e-7, rel_tol=1e-6, floor=1e-9):
             arr, flat = m0, 1 + (idx - 6 * n)
             h = rel_step * m0[flat]
         base = arr.ravel()[flat]
-        arr.ravel()[flat] = base + h
-        pp = final(p0, v0, m0)
-        arr.ravel()[flat] = base - h
-        pm = final(p0, v0, m0)
-        # sum of (a^2 - b^2) as (a - b)(a + b): no cancellation between two
-        # nearly equal totals
-        a = pp[:, first:] - tgt[:, first:]
-        b = pm[:, first:] - tgt[:, first:]
-        fds.append(np.sum((pp[:, first:] - pm[:, first:]) * (a + b)) / (2 * h))
+
+        def at(k):
+            arr.ravel()[flat] = base + k * h
+            out = final(p0, v0, m0)
+            arr.ravel()[flat] = base
+            return out
+
+        p1, m1 = at(1), at(-1)
+        d1 = _loss_diff(p1, m1, tgt, first)
+        if order == 2:
+            fds.append(d1 / (2 * h))
+        else:
+            d2 = _loss_diff(at(2), at(-2), tgt, first)
+            fds.append((8 * d1 - d2) / (12 * h))
     fds = np.array(fds)
     adj = grad[coords]
     scale = np.abs(fds).max()
     ok = (np.abs(adj - fds) <= rel_tol * np.abs(fds)) | (np.abs(adj - fds) <= floor * scale)
     for i, c in enumerate(coords):
-        print(f"coord {c:6d}: adjoint {adj[i]: .10e}  fd {fds[i]: .10e}  "
-              f"rel {abs(adj[i] - fds[i]) / max(abs(fds[i]), 1e-300):.1e}", flush=True)
+        print(f"order {order} step {rel_step:g} coord {c:6d}: adjoint {adj[i]: .10e}  "
+              f"fd {fds[i]: .10e}  rel {abs(adj[i] - fds[i]) / max(abs(fds[i]), 1e-300):.1e}",
+              flush=True)
     return ok, adj, fds
 
 
 def test_adjoint_vs_finite_differences_prefix():
+    """Loss of the adjoint workload over a 1000-step prefix.
+
+    The loss's gradient is proportional to the 1e-8 AU target offset, so the
+    O(h^2) error of the two-point quotient (~ h^2 d^2r/dx^2 / 1e-8) is large
+    at any step that lifts it above roundoff; a fourth-order central stencil
+    removes that term.  Its remaining error is the roundoff of the forward
+    runs (last-bit changes in every other body's trajectory, divided by h),
+    estimated per coordinate by the spread between the stencil at relative
+    steps 1e-6 and 1e-5.  The adjoint must agree with the 1e-6 stencil to
+    1e-6 relative, or within twice that estimated FD error when the estimate
+    itself is below 1e-4 relative (small gradients, where the absolute noise
+    dominates); entries below 1e-9 of the largest sampled gradient are
+    negligible.  The two-point quotient at relative step 1e-7 is reported and
+    checked at the 1e-4 level its own error allows."""
     s = S.config(4)
     rng = np.random.default_rng(5)
     n = s.n
     coords = np.sort(np.concatenate([
-        rng.choice(np.arange(3 * 31, 3 * n), 6, replace=False),           # asteroid positions
-        3 * n + rng.choice(np.arange(3 * 31, 3 * n), 4, replace=False),    # asteroid velocities
-        rng.choice(np.arange(0, 3 * 31), 2, replace=False),                # Sun/major positions
+        rng.choice(np.arange(3 * 31, 3 * n), 6, replace=False),           # positions
+        3 * n + rng.choice(np.arange(3 * 31, 3 * n), 4, replace=False),    # velocities
+        rng.choice(np.arange(0, 3 * 31), 2, replace=False),                # low-index positions
         [6 * n + int(np.argmax(s.mass[1:31]))],                            # heaviest major mass
     ]))
-    # At a relative step of 1e-5 the difference quotient is far above the
-    # roundoff noise of the two forward runs and its truncation error is
-    # O(h^2) ~ 1e-10: the adjoint must agree to 1e-6.
-    ok, adj, fds = _fd_check(s, 1000, 100, coords, rel_step=1e-5)
-    assert ok.all()
-    # At 1e-7 the quotient carries the forward runs' roundoff (last-bit
-    # differences in every other body's trajectory, scaled by 1/h): agreement
-    # is limited by that noise, checked at a correspondingly looser level.
-    ok7, adj7, fds7 = _fd_check(s, 1000, 100, coords, rel_step=1e-7, rel_tol=1e-4)
+    _, adj, fd6 = _fd_check(s, 1000, 100, coords, rel_step=1e-6, order=4)
+    _, _, fd5 = _fd_check(s, 1000, 100, coords, rel_step=1e-5, order=4)
+    err = np.abs(adj - fd6)
+    unc = np.abs(fd6 - fd5)
+    scale = np.abs(fd6).max()
+    ok = ((err <= 1e-6 * np.abs(fd6)) | (err <= 1e-9 * scale)
+          | ((err <= 1e-6 * np.abs(fd6) + 2 * unc) & (unc <= 1e-4 * np.abs(fd6))))
+    assert ok.all(), list(zip(coords[~ok], err[~ok] / np.abs(fd6[~ok]), unc[~ok] / np.abs(fd6[~ok])))
+    assert np.median(err / np.abs(fd6)) <= 1e-6
+    ok7, _, _ = _fd_check(s, 1000, 100, coords, rel_step=1e-7, order=2, rel_tol=1e-4)
     assert ok7.all()
 
 
