@@ -41,12 +41,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="solar-10425",
-                    choices=["solar-10425", "solar-131", "solar-131072", "ensemble", "adjoint"])
+                    choices=["solar-10425", "solar-131", "solar-131072", "ensemble", "adjoint",
+                             "copy"])
     ap.add_argument("--no-tune", action="store_true", help="use the heuristic tile shapes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU time budget of the oracle sample")
     ap.add_argument("--fd-coords", type=int, default=64, help="adjoint workload: FD coordinates")
+    ap.add_argument("--tile", default=None, help="fix the FP64 force tile as T,W,C (skips autotune)")
+    ap.add_argument("--split-tile", default=None, help="fix the split force tile as T,W,C")
     return ap.parse_args()
 
 
@@ -87,6 +90,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    if args.workload == "copy":
+        return bench_copy(torch, dev)
     if args.workload == "ensemble":
         return bench_ensemble(args, S, nb, torch, np, dev)
     if args.workload == "adjoint":
@@ -108,8 +113,10 @@ def bench_single(args, k, S, nb, torch, np_, dev):
     pos0, vel0, m = _t(s.pos, torch, dev), _t(s.vel, torch, dev), _t(s.mass, torch, dev)
 
     tiles = {}
-    for prec in ("fp64", "split"):
-        if not args.no_tune:
+    for prec, fixed in (("fp64", args.tile), ("split", args.split_tile)):
+        if fixed:
+            nb.set_tile(0, prec, n, *[int(x) for x in fixed.split(",")])
+        elif not args.no_tune:
             tile, ms = nb.autotune(pos0, m, G, prec)
             log(f"autotune {prec}: {tile} {ms:.4f} ms per force pass")
         tiles[prec] = nb.get_tile(0, prec, n)
@@ -224,6 +231,26 @@ def cpu_baseline(s, budget_s, k):
             "sample": f"first {steps} steps of the same {n}-body run ({steps + 1} force passes, "
                       f"{t:.1f} s)",
             "host_cpus": os.cpu_count()}
+
+
+def bench_copy(torch, dev):
+    """A plain device copy of known size: the reference that scales the
+    FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    nbytes = 256 << 20
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        y.copy_(x)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / 10
+    print(json.dumps({"metric": "device copy", "bytes_read": nbytes, "bytes_written": nbytes,
+                      "ms": ms, "GB_per_s": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def bench_ensemble(args, S, nb, torch, np, dev):

@@ -144,16 +144,20 @@ int32_t nbody_momenta(const double* pos, const double* vel, const double* mass,
 int32_t nbody_get_flags(void* workspace, void* stream, int32_t clear, int32_t* flags_host);
 
 /* Tile shape of the force pass: targets per lane (1, 2, 4), waves per
- * workgroup (1, 2, 4, 8) and source chunks (1..64). */
+ * workgroup (1, 2, 4, 8), source chunks (1..64) and how sources reach the
+ * lanes (variant 0: staged through LDS; 1: read once per wavefront into
+ * scalar registers; the adjoint pass supports variant 0 only). */
 typedef struct {
     int32_t targets_per_lane;
     int32_t waves;
     int32_t chunks;
+    int32_t variant;
 } nbody_tile;
 
 /* The tile shape the library will use for (kind, precision, n): the tuned
  * one if nbody_autotune ran for that size class, else a heuristic.
- * kind: 0 = force pass, 1 = adjoint pass. */
+ * kind: 0 = force pass, 1 = adjoint pass, 2 = batched ensemble (n is
+ * ignored; chunks are chosen per system). */
 int32_t nbody_get_tile(int32_t kind, int32_t precision, int64_t n, nbody_tile* tile_host);
 
 /* Force a tile shape for (kind, precision, n's size class); shapes outside

@@ -34,11 +34,11 @@ class NBodyError(RuntimeError):
 
 class Tile(ctypes.Structure):
     _fields_ = [("targets_per_lane", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("chunks", ctypes.c_int32)]
+                ("chunks", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
     def as_dict(self):
         return {"targets_per_lane": self.targets_per_lane, "waves": self.waves,
-                "chunks": self.chunks}
+                "chunks": self.chunks, "variant": self.variant}
 
 
 _lib = None

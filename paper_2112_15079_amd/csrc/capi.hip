@@ -105,7 +105,7 @@ Tile pick_tile(int kind, int prec, int64_t n)
 // workspace layout
 
 struct Layout {
-    size_t flags = 0, part = 0, alt = 0, perm = 0, nmaj = 0, offs = 0, pos_c = 0, vel_c = 0,
+    size_t flags = 0, part = 0, alt = 0, gm = 0, perm = 0, nmaj = 0, offs = 0, pos_c = 0, vel_c = 0,
            mass_c = 0, alt_c = 0, rows = 0, units = 0, bchunks = 0, ck = 0, seg = 0, lam_r = 0,
            lam_v = 0, g_m = 0, u = 0, vtmp = 0, total = 0;
 };
@@ -132,6 +132,7 @@ Layout layout(int op, int64_t n, int32_t ns, int64_t steps, int64_t K, int prec)
     const int planes = (op == NBODY_OP_ADJOINT) ? 4 : 3;
     L.part = a.take((size_t)cap * planes * n * d);
     L.alt = a.take(3 * n * d);
+    L.gm = a.take(n * d);
     if (prec == NBODY_SPLIT && op != NBODY_OP_ADJOINT && op != NBODY_OP_ENERGY) {
         L.perm = a.take(n * sizeof(int32_t));
         L.nmaj = a.take((size_t)ns * sizeof(int64_t));
@@ -303,6 +304,7 @@ struct StepPlan {
     int64_t n = 0;
     double G = 0, dt = 0;
     const double* mass = nullptr;   // in the working order
+    const double* gm = nullptr;     // G * mass, same order
     double* vel = nullptr;          // working velocity
     double* buf[2] = {nullptr, nullptr};   // position ping-pong
     double* part = nullptr;
@@ -318,10 +320,10 @@ struct StepPlan {
 int force(const StepPlan& P, const double* pos, hipStream_t s)
 {
     if (P.units)
-        NB_HIP(launch_force_batched(P.prec, P.tile, pos, P.mass, P.n, P.G, P.units, P.num_units,
-                                    P.nmaj, P.grid, P.part, s));
+        NB_HIP(launch_force_batched(P.prec, P.tile, pos, P.mass, P.gm, P.n, P.G, P.units,
+                                    P.num_units, P.nmaj, P.grid, P.part, s));
     else
-        NB_HIP(launch_force(P.prec, P.tile, pos, P.mass, P.n, P.nmaj, P.G, P.part, s));
+        NB_HIP(launch_force(P.prec, P.tile, pos, P.mass, P.gm, P.n, P.nmaj, P.G, P.part, s));
     return NBODY_OK;
 }
 
@@ -421,8 +423,10 @@ int32_t nbody_accel(const double* pos, const double* vel, const double* mass, in
     const int chunks = effective_chunks(n, tile);
     double* part = at<double>(workspace, L.part);
     uint32_t* flags = at<uint32_t>(workspace, L.flags);
+    double* gm = at<double>(workspace, L.gm);
     if (precision == NBODY_FP64) {
-        NB_HIP(launch_force(0, tile, pos, mass, n, nullptr, G, part, s));
+        NB_HIP(launch_scale(mass, G, n, gm, s));
+        NB_HIP(launch_force(0, tile, pos, mass, gm, n, nullptr, G, part, s));
         NB_HIP(launch_step(part, chunks, nullptr, n, nullptr, nullptr, nullptr, acc_out, 0.0,
                            kStoreAcc, flags, s));
         return NBODY_OK;
@@ -434,7 +438,8 @@ int32_t nbody_accel(const double* pos, const double* vel, const double* mass, in
     double* acc_c = at<double>(workspace, L.alt_c);
     NB_HIP(launch_gather(perm, n, pos, pos_c, 3, s));
     NB_HIP(launch_gather(perm, n, mass, mass_c, 1, s));
-    NB_HIP(launch_force(1, tile, pos_c, mass_c, n, at<int64_t>(workspace, L.nmaj), G, part, s));
+    NB_HIP(launch_scale(mass_c, G, n, gm, s));
+    NB_HIP(launch_force(1, tile, pos_c, mass_c, gm, n, at<int64_t>(workspace, L.nmaj), G, part, s));
     NB_HIP(launch_step(part, chunks, nullptr, n, nullptr, nullptr, nullptr, acc_c, 0.0,
                        kStoreAcc, flags, s));
     NB_HIP(launch_scatter(perm, n, acc_c, acc_out, 3, s));
@@ -466,9 +471,12 @@ int32_t nbody_verlet_run(double* pos, double* vel, const double* mass, int64_t n
     P.part = at<double>(workspace, L.part);
     P.flags = at<uint32_t>(workspace, L.flags);
     double* alt = at<double>(workspace, L.alt);
+    double* gm = at<double>(workspace, L.gm);
+    P.gm = gm;
     if (precision == NBODY_FP64) {
         P.mass = mass;
         P.vel = vel;
+        NB_HIP(launch_scale(mass, G, n, gm, s));
         // r_steps must land in the caller's buffer: buf[steps & 1] = pos.
         if (steps & 1) {
             P.buf[0] = alt;
@@ -489,6 +497,7 @@ int32_t nbody_verlet_run(double* pos, double* vel, const double* mass, int64_t n
     NB_HIP(launch_gather(perm, n, pos, pos_c, 3, s));
     NB_HIP(launch_gather(perm, n, vel, vel_c, 3, s));
     NB_HIP(launch_gather(perm, n, mass, mass_c, 1, s));
+    NB_HIP(launch_scale(mass_c, G, n, gm, s));
     P.mass = mass_c;
     P.vel = vel_c;
     P.buf[0] = pos_c;
@@ -544,20 +553,25 @@ int32_t nbody_get_flags(void* workspace, void* stream, int32_t clear, int32_t* f
 int32_t nbody_get_tile(int32_t kind, int32_t precision, int64_t n, nbody_tile* tile_host)
 {
     g_err.clear();
-    if (!tile_host || (kind != 0 && kind != 1) || n < 1) return fail(NBODY_EINVAL, "bad arguments");
+    if (!tile_host || kind < 0 || kind > 2 || (kind != 2 && n < 1))
+        return fail(NBODY_EINVAL, "bad arguments");
+    if (kind == 2) n = 0;
     const Tile t = pick_tile(kind, precision, n);
     tile_host->targets_per_lane = t.tpl;
     tile_host->waves = t.waves;
     tile_host->chunks = t.chunks;
+    tile_host->variant = t.variant;
     return NBODY_OK;
 }
 
 int32_t nbody_set_tile(int32_t kind, int32_t precision, int64_t n, const nbody_tile* tile_host)
 {
     g_err.clear();
-    if (!tile_host || (kind != 0 && kind != 1) || n < 1) return fail(NBODY_EINVAL, "bad arguments");
-    Tile t{tile_host->targets_per_lane, tile_host->waves, tile_host->chunks};
-    if (!tile_supported(t) || (kind == 1 && (t.tpl > 2 || t.waves > 4)))
+    if (!tile_host || kind < 0 || kind > 2 || (kind != 2 && n < 1))
+        return fail(NBODY_EINVAL, "bad arguments");
+    if (kind == 2) n = 0;
+    Tile t{tile_host->targets_per_lane, tile_host->waves, tile_host->chunks, tile_host->variant};
+    if (!tile_supported(t) || (kind == 1 && (t.tpl > 2 || t.waves > 4 || t.variant != 0)))
         return fail(NBODY_EINVAL, "unsupported tile (%d, %d, %d)", t.tpl, t.waves, t.chunks);
     std::lock_guard<std::mutex> lk(g_mu);
     g_tiles[std::make_tuple(kind, precision, size_class(n))] = t;
@@ -615,8 +629,10 @@ int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const doubl
     P.G = G;
     P.dt = dt;
     P.mass = mass;
+    P.gm = at<double>(workspace, L.gm);
     P.part = part;
     P.flags = flags;
+    NB_HIP(launch_scale(mass, G, n, at<double>(workspace, L.gm), s));
     NB_HIP(hipMemcpyAsync(ck_r(0), pos0, b3, hipMemcpyDeviceToDevice, s));
     NB_HIP(hipMemcpyAsync(ck_v(0), vel0, b3, hipMemcpyDeviceToDevice, s));
     for (int64_t c = 0; c < nck; ++c) {
@@ -702,6 +718,7 @@ std::shared_ptr<BatchPlan> batch_plan(const int64_t* offs, int32_t ns, const Til
     std::vector<int64_t> key(offs, offs + ns + 1);
     key.push_back(t.tpl);
     key.push_back(t.waves);
+    key.push_back(t.variant);
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_batch.find(key);
     if (it != g_batch.end()) return it->second;
@@ -804,9 +821,12 @@ int32_t nbody_verlet_run_batched(double* pos, double* vel, const double* mass,
     P.grid = (int)std::min<int64_t>(P.num_units, (int64_t)cus * (16 / t.waves));
     P.bchunks = bchunks;
     double* alt = at<double>(workspace, L.alt);
+    double* gm = at<double>(workspace, L.gm);
+    P.gm = gm;
     if (precision == NBODY_FP64) {
         P.mass = mass;
         P.vel = vel;
+        NB_HIP(launch_scale(mass, G, n, gm, s));
         if (steps & 1) {
             P.buf[0] = alt;
             P.buf[1] = pos;
@@ -827,6 +847,7 @@ int32_t nbody_verlet_run_batched(double* pos, double* vel, const double* mass,
     NB_HIP(launch_gather(perm, n, pos, pos_c, 3, s));
     NB_HIP(launch_gather(perm, n, vel, vel_c, 3, s));
     NB_HIP(launch_gather(perm, n, mass, mass_c, 1, s));
+    NB_HIP(launch_scale(mass_c, G, n, gm, s));
     P.mass = mass_c;
     P.vel = vel_c;
     P.buf[0] = pos_c;
@@ -846,6 +867,7 @@ namespace {
 struct Bench {
     const double* pos = nullptr;
     const double* mass = nullptr;
+    const double* gm = nullptr;
     const int64_t* nmaj = nullptr;
     double* part = nullptr;
     double* scratch = nullptr;
@@ -876,6 +898,9 @@ int bench_prepare(int32_t kind, int32_t precision, const double* pos, const doub
         b->nmaj = at<int64_t>(workspace, L.nmaj);
     }
     if (kind == 1) NB_HIP(launch_fill(b->scratch, 1e-3, 3 * n, s));   // cotangent for timing
+    double* gm = at<double>(workspace, L.gm);
+    NB_HIP(launch_scale(b->mass, G, n, gm, s));
+    b->gm = gm;
     return NBODY_OK;
 }
 
@@ -895,7 +920,7 @@ int32_t nbody_time_force(int32_t kind, int32_t precision, const double* pos, con
                          s, &b));
     const Tile t = pick_tile(kind, precision, n);
     auto once = [&]() -> int {
-        if (kind == 0) NB_HIP(launch_force(precision, t, b.pos, b.mass, n, b.nmaj, G, b.part, s));
+        if (kind == 0) NB_HIP(launch_force(precision, t, b.pos, b.mass, b.gm, n, b.nmaj, G, b.part, s));
         else           NB_HIP(launch_vjp(t, b.pos, b.mass, b.scratch, n, G, b.part, s));
         return NBODY_OK;
     };
@@ -952,7 +977,10 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
             }
             std::sort(cs.begin(), cs.end());
             cs.erase(std::unique(cs.begin(), cs.end()), cs.end());
-            for (int c : cs) cands.push_back(Tile{t.tpl, t.waves, c});
+            for (int c : cs) {
+                cands.push_back(Tile{t.tpl, t.waves, c, 0});
+                if (kind == 0) cands.push_back(Tile{t.tpl, t.waves, c, 1});
+            }
         }
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -960,7 +988,7 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
     NB_HIP(hipEventCreate(&e1));
     auto once = [&](const Tile& t) -> int {
         if (kind == 0) {
-            NB_HIP(launch_force(precision, t, pos_w, mass_w, n, nmaj, G, part, s));
+            NB_HIP(launch_force(precision, t, pos_w, mass_w, b.gm, n, nmaj, G, part, s));
             NB_HIP(launch_step(part, effective_chunks(n, t), nullptr, n, nullptr, nullptr, nullptr,
                                scratch, 0.0, kStoreAcc, nullptr, s));
         } else {
@@ -1002,6 +1030,7 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
         best_host->targets_per_lane = best.tpl;
         best_host->waves = best.waves;
         best_host->chunks = best.chunks;
+        best_host->variant = best.variant;
     }
     if (best_ms_host) *best_ms_host = best_ms;
     return NBODY_OK;

@@ -14,9 +14,10 @@ namespace nb {
 // contiguous pieces (grid.y), each summed separately; the step epilogue adds
 // the pieces in a fixed order, so results do not depend on scheduling.
 struct Tile {
-    int tpl;     // targets per lane: 1, 2, 4
-    int waves;   // wavefronts per workgroup: 1, 2, 4, 8
-    int chunks;  // source chunks, 1..64
+    int tpl;          // targets per lane: 1, 2, 4
+    int waves;        // wavefronts per workgroup: 1, 2, 4, 8
+    int chunks;       // source chunks, 1..64
+    int variant = 0;  // 0: sources staged in LDS; 1: sources as scalar operands
 };
 
 constexpr int kMaxChunks = 64;
@@ -38,8 +39,10 @@ int effective_chunks(int64_t n, const Tile& t);
 // Newton-refined reciprocal square root, sources [n_major, n) in FP32 with
 // Kahan compensation.
 // nmaj: device pointer to the number of FP64-class sources (split form only).
+// gm: G * mass plane (required by variant 1; the LDS variant scales on load).
 hipError_t launch_force(int precision, const Tile& tile, const double* pos, const double* mass,
-                        int64_t n, const int64_t* nmaj, double G, double* part, hipStream_t s);
+                        const double* gm, int64_t n, const int64_t* nmaj, double G, double* part,
+                        hipStream_t s);
 
 // Batched form: `units` work items of (system, target block, chunk), see
 // kernels_force.hip.
@@ -53,7 +56,7 @@ struct BatchUnit {
     int32_t pad;
 };
 hipError_t launch_force_batched(int precision, const Tile& tile, const double* pos,
-                                const double* mass, int64_t n_total, double G,
+                                const double* mass, const double* gm, int64_t n_total, double G,
                                 const BatchUnit* units, int64_t num_units, const int64_t* nmaj,
                                 int grid, double* part, hipStream_t s);
 

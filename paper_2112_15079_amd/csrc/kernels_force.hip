@@ -258,6 +258,204 @@ __device__ __forceinline__ void force_block(const double* __restrict__ pos,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Scalar-operand variant.  Every lane of a wavefront needs the same source,
+// so the source coordinates and G m are fetched once per wavefront into
+// scalar registers (one s_load_dwordx16 brings 8 consecutive values of a
+// plane through the scalar data cache) and enter the vector instructions as
+// scalar operands: no LDS staging, no barriers, no per-lane copies.  The
+// mass plane is pre-multiplied by G (gm).
+constexpr int kSGroup = 8;
+
+template <int T, bool MASK, bool NEWTON1>
+__device__ __forceinline__ void pair_f64(double sx, double sy, double sz, double sg, int64_t j,
+                                         const Targets<T>& tg, double (&ax)[T], double (&ay)[T],
+                                         double (&az)[T], const PolyConst& c)
+{
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const double dx = sx - tg.x[t];
+        const double dy = sy - tg.y[t];
+        const double dz = sz - tg.z[t];
+        const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+        double f = NEWTON1 ? gm_rinv3_newton1(r2, sg) : gm_rinv3_f64(r2, sg, c);
+        if (MASK) f = (j == tg.id[t]) ? 0.0 : f;
+        ax[t] = __builtin_fma(f, dx, ax[t]);
+        ay[t] = __builtin_fma(f, dy, ay[t]);
+        az[t] = __builtin_fma(f, dz, az[t]);
+    }
+}
+
+template <int T, bool MASK>
+__device__ __forceinline__ void pair_small(double sx, double sy, double sz, double sg, int64_t j,
+                                           const Targets<T>& tg, float (&bx)[T], float (&by)[T],
+                                           float (&bz)[T])
+{
+    const float gm = (float)sg;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const float dx = (float)(sx - tg.x[t]);
+        const float dy = (float)(sy - tg.y[t]);
+        const float dz = (float)(sz - tg.z[t]);
+        const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+        const float y = __builtin_amdgcn_rsqf(r2);
+        float w = gm * (y * y * y);
+        if (MASK) w = (j == tg.id[t]) ? 0.f : w;
+        bx[t] = __builtin_fmaf(w, dx, bx[t]);
+        by[t] = __builtin_fmaf(w, dy, by[t]);
+        bz[t] = __builtin_fmaf(w, dz, bz[t]);
+    }
+}
+
+template <int T>
+__device__ __forceinline__ void kahan_flush(Kahan<T>& k, float (&bx)[T], float (&by)[T],
+                                            float (&bz)[T])
+{
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        kahan_add(k.sx[t], k.cx[t], bx[t]);
+        kahan_add(k.sy[t], k.cy[t], by[t]);
+        kahan_add(k.sz[t], k.cz[t], bz[t]);
+        bx[t] = 0.f; by[t] = 0.f; bz[t] = 0.f;
+    }
+}
+
+template <int T, int W, bool SPLIT>
+__device__ __forceinline__ void force_block_s(const double* __restrict__ pos,
+                                              const double* __restrict__ gm, int64_t stride,
+                                              int64_t n, int64_t n_major, int64_t tb0,
+                                              int64_t jbeg, int64_t jend,
+                                              double* __restrict__ part_c)
+{
+    constexpr int NT = 64 * W;
+    const int tid = threadIdx.x;
+    Targets<T> tg;
+    load_targets<T, NT>(tg, pos, stride, n, tb0, tid);
+    double ax[T], ay[T], az[T];
+    Kahan<T> k;
+    float bx[T], by[T], bz[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        ax[t] = 0.0; ay[t] = 0.0; az[t] = 0.0;
+        k.sx[t] = 0.f; k.sy[t] = 0.f; k.sz[t] = 0.f;
+        k.cx[t] = 0.f; k.cy[t] = 0.f; k.cz[t] = 0.f;
+        bx[t] = 0.f; by[t] = 0.f; bz[t] = 0.f;
+    }
+    const PolyConst c32 = {vreg_const(1.875), vreg_const(1.5)};
+    const int64_t tend = tb0 + (int64_t)NT * T;
+    const double* __restrict__ px = pos;
+    const double* __restrict__ py = pos + stride;
+    const double* __restrict__ pz = pos + 2 * stride;
+    int small_groups = 0;
+    int64_t j = jbeg;
+    for (; j + kSGroup <= jend; j += kSGroup) {
+        double xs[kSGroup], ys[kSGroup], zs[kSGroup], gs[kSGroup];
+#pragma unroll
+        for (int u = 0; u < kSGroup; ++u) {
+            xs[u] = px[j + u];
+            ys[u] = py[j + u];
+            zs[u] = pz[j + u];
+            gs[u] = gm[j + u];
+        }
+        const bool diag = (j < tend) && (tb0 < j + kSGroup);
+        if (!SPLIT || j + kSGroup <= n_major) {
+            if (diag) {
+#pragma unroll
+                for (int u = 0; u < kSGroup; ++u)
+                    pair_f64<T, true, SPLIT>(xs[u], ys[u], zs[u], gs[u], j + u, tg, ax, ay, az, c32);
+            } else {
+#pragma unroll
+                for (int u = 0; u < kSGroup; ++u)
+                    pair_f64<T, false, SPLIT>(xs[u], ys[u], zs[u], gs[u], j + u, tg, ax, ay, az, c32);
+            }
+        } else if (j >= n_major) {
+            if (diag) {
+#pragma unroll
+                for (int u = 0; u < kSGroup; ++u)
+                    pair_small<T, true>(xs[u], ys[u], zs[u], gs[u], j + u, tg, bx, by, bz);
+            } else {
+#pragma unroll
+                for (int u = 0; u < kSGroup; ++u)
+                    pair_small<T, false>(xs[u], ys[u], zs[u], gs[u], j + u, tg, bx, by, bz);
+            }
+            // a compensated add every kBlk small sources
+            if (++small_groups == kBlk / kSGroup) {
+                kahan_flush(k, bx, by, bz);
+                small_groups = 0;
+            }
+        } else {
+            for (int u = 0; u < kSGroup; ++u) {
+                if (j + u < n_major)
+                    pair_f64<T, true, true>(xs[u], ys[u], zs[u], gs[u], j + u, tg, ax, ay, az, c32);
+                else
+                    pair_small<T, true>(xs[u], ys[u], zs[u], gs[u], j + u, tg, bx, by, bz);
+            }
+        }
+    }
+    for (; j < jend; ++j) {
+        const double sx = px[j], sy = py[j], sz = pz[j], sg = gm[j];
+        if (!SPLIT || j < n_major)
+            pair_f64<T, true, SPLIT>(sx, sy, sz, sg, j, tg, ax, ay, az, c32);
+        else
+            pair_small<T, true>(sx, sy, sz, sg, j, tg, bx, by, bz);
+    }
+    if (SPLIT) kahan_flush(k, bx, by, bz);
+
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int64_t p = tb0 + (int64_t)t * NT + tid;
+        if (p < n) {
+            double vx = ax[t], vy = ay[t], vz = az[t];
+            if (SPLIT) {
+                vx += (double)k.sx[t] - (double)k.cx[t];
+                vy += (double)k.sy[t] - (double)k.cy[t];
+                vz += (double)k.sz[t] - (double)k.cz[t];
+            }
+            part_c[p] = vx;
+            part_c[stride + p] = vy;
+            part_c[2 * stride + p] = vz;
+        }
+    }
+}
+
+template <int T, int W, bool SPLIT>
+__global__ __launch_bounds__(64 * W) void k_force_s(const double* __restrict__ pos,
+                                                    const double* __restrict__ gm, int64_t n,
+                                                    const int64_t* __restrict__ nmaj,
+                                                    int64_t chunk_len, double* __restrict__ part)
+{
+    constexpr int NT = 64 * W;
+    const int64_t n_major = SPLIT ? nmaj[0] : 0;
+    const int64_t tb0 = (int64_t)blockIdx.x * NT * T;
+    const int64_t c = blockIdx.y;
+    const int64_t jbeg = c * chunk_len;
+    const int64_t jend = (jbeg + chunk_len < n) ? jbeg + chunk_len : n;
+    force_block_s<T, W, SPLIT>(pos, gm, n, n, n_major, tb0, jbeg, jend, part + c * 3 * n);
+}
+
+template <int T, int W, bool SPLIT>
+__global__ __launch_bounds__(64 * W) void k_force_s_batched(const double* __restrict__ pos,
+                                                            const double* __restrict__ gm,
+                                                            int64_t n_total,
+                                                            const BatchUnit* __restrict__ units,
+                                                            int64_t num_units,
+                                                            const int64_t* __restrict__ nmaj,
+                                                            double* __restrict__ part)
+{
+    constexpr int NT = 64 * W;
+    for (int64_t u = blockIdx.x; u < num_units; u += gridDim.x) {
+        const BatchUnit w = units[u];
+        const int64_t n_major = SPLIT ? nmaj[w.sys] : 0;
+        const int64_t n = w.n;
+        const int64_t chunk_len = ((n + w.chunks - 1) / w.chunks + NT - 1) / NT * NT;
+        const int64_t jbeg = (int64_t)w.chunk * chunk_len;
+        const int64_t jend = (jbeg + chunk_len < n) ? jbeg + chunk_len : n;
+        const int64_t tb0 = (int64_t)w.tblock * NT * T;
+        force_block_s<T, W, SPLIT>(pos + w.body0, gm + w.body0, n_total, n, n_major, tb0, jbeg,
+                                   jend, part + (int64_t)w.chunk * 3 * n_total + w.body0);
+    }
+}
+
 template <int T, int W, bool SPLIT>
 __global__ __launch_bounds__(64 * W) void k_force(const double* __restrict__ pos,
                                                   const double* __restrict__ mass, int64_t n,
@@ -308,7 +506,8 @@ bool tile_supported(const Tile& t)
 {
     const bool tpl_ok = t.tpl == 1 || t.tpl == 2 || t.tpl == 4;
     const bool w_ok = t.waves == 1 || t.waves == 2 || t.waves == 4 || t.waves == 8;
-    return tpl_ok && w_ok && t.chunks >= 1 && t.chunks <= kMaxChunks;
+    return tpl_ok && w_ok && t.chunks >= 1 && t.chunks <= kMaxChunks &&
+           (t.variant == 0 || t.variant == 1);
 }
 
 int64_t chunk_length(int64_t n, const Tile& t)
@@ -319,12 +518,21 @@ int64_t chunk_length(int64_t n, const Tile& t)
 }
 
 template <int T, int W>
-static hipError_t launch_tw(int precision, const double* pos, const double* mass, int64_t n,
-                            const int64_t* nmaj, double G, int64_t chunk_len, int chunks,
-                            double* part, hipStream_t s)
+static hipError_t launch_tw(int precision, int variant, const double* pos, const double* mass,
+                            const double* gm, int64_t n, const int64_t* nmaj, double G,
+                            int64_t chunk_len, int chunks, double* part, hipStream_t s)
 {
     constexpr int NT = 64 * W;
     const dim3 grid((unsigned)((n + (int64_t)NT * T - 1) / ((int64_t)NT * T)), (unsigned)chunks);
+    if (variant == 1) {
+        if (precision == 0)
+            hipLaunchKernelGGL((k_force_s<T, W, false>), grid, dim3(NT), 0, s, pos, gm, n, nmaj,
+                               chunk_len, part);
+        else
+            hipLaunchKernelGGL((k_force_s<T, W, true>), grid, dim3(NT), 0, s, pos, gm, n, nmaj,
+                               chunk_len, part);
+        return hipGetLastError();
+    }
     if (precision == 0)
         hipLaunchKernelGGL((k_force<T, W, false>), grid, dim3(NT), 0, s, pos, mass, n, nmaj,
                            chunk_len, G, part);
@@ -335,12 +543,21 @@ static hipError_t launch_tw(int precision, const double* pos, const double* mass
 }
 
 template <int T, int W>
-static hipError_t launch_batched_tw(int precision, const double* pos, const double* mass,
-                                    int64_t n_total, double G, const BatchUnit* units,
-                                    int64_t num_units, const int64_t* nmaj, int grid,
-                                    double* part, hipStream_t s)
+static hipError_t launch_batched_tw(int precision, int variant, const double* pos,
+                                    const double* mass, const double* gm, int64_t n_total,
+                                    double G, const BatchUnit* units, int64_t num_units,
+                                    const int64_t* nmaj, int grid, double* part, hipStream_t s)
 {
     constexpr int NT = 64 * W;
+    if (variant == 1) {
+        if (precision == 0)
+            hipLaunchKernelGGL((k_force_s_batched<T, W, false>), dim3(grid), dim3(NT), 0, s, pos,
+                               gm, n_total, units, num_units, nmaj, part);
+        else
+            hipLaunchKernelGGL((k_force_s_batched<T, W, true>), dim3(grid), dim3(NT), 0, s, pos,
+                               gm, n_total, units, num_units, nmaj, part);
+        return hipGetLastError();
+    }
     if (precision == 0)
         hipLaunchKernelGGL((k_force_batched<T, W, false>), dim3(grid), dim3(NT), 0, s, pos, mass,
                            n_total, G, units, num_units, nmaj, part);
@@ -360,27 +577,31 @@ int effective_chunks(int64_t n, const Tile& t)
 }
 
 hipError_t launch_force(int precision, const Tile& tile, const double* pos, const double* mass,
-                        int64_t n, const int64_t* nmaj, double G, double* part, hipStream_t s)
+                        const double* gm, int64_t n, const int64_t* nmaj, double G, double* part,
+                        hipStream_t s)
 {
+    if (tile.variant == 1 && !gm) return hipErrorInvalidValue;
     const int64_t L = chunk_length(n, tile);
     const int chunks = effective_chunks(n, tile);
 #define NB_CASE(TT, WW)                                                                  \
     if (tile.tpl == TT && tile.waves == WW)                                              \
-        return launch_tw<TT, WW>(precision, pos, mass, n, nmaj, G, L, chunks, part, s);
+        return launch_tw<TT, WW>(precision, tile.variant, pos, mass, gm, n, nmaj, G, L, chunks, \
+                                 part, s);
     NB_TILE_CASES(NB_CASE)
 #undef NB_CASE
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_force_batched(int precision, const Tile& tile, const double* pos,
-                                const double* mass, int64_t n_total, double G,
+                                const double* mass, const double* gm, int64_t n_total, double G,
                                 const BatchUnit* units, int64_t num_units, const int64_t* nmaj,
                                 int grid, double* part, hipStream_t s)
 {
+    if (tile.variant == 1 && !gm) return hipErrorInvalidValue;
 #define NB_CASE(TT, WW)                                                                   \
     if (tile.tpl == TT && tile.waves == WW)                                               \
-        return launch_batched_tw<TT, WW>(precision, pos, mass, n_total, G, units, num_units, \
-                                         nmaj, grid, part, s);
+        return launch_batched_tw<TT, WW>(precision, tile.variant, pos, mass, gm, n_total, G, \
+                                         units, num_units, nmaj, grid, part, s);
     NB_TILE_CASES(NB_CASE)
 #undef NB_CASE
     return hipErrorInvalidValue;

@@ -199,8 +199,8 @@ def get_tile(kind, precision, n):
     return t.as_dict()
 
 
-def set_tile(kind, precision, n, targets_per_lane, waves, chunks):
-    t = C.Tile(int(targets_per_lane), int(waves), int(chunks))
+def set_tile(kind, precision, n, targets_per_lane, waves, chunks, variant=0):
+    t = C.Tile(int(targets_per_lane), int(waves), int(chunks), int(variant))
     C.check(C.load().nbody_set_tile(int(kind), _prec(precision), int(n), ctypes.byref(t)),
             "nbody_set_tile")
 

@@ -129,13 +129,21 @@ def test_tile_table():
     t = C.Tile()
     assert lib.nbody_get_tile(0, 0, 10425, ctypes.byref(t)) == C.NBODY_OK
     assert t.targets_per_lane in (1, 2, 4) and t.waves in (1, 2, 4, 8) and 1 <= t.chunks <= 64
-    want = C.Tile(4, 2, 7)
+    want = C.Tile(4, 2, 7, 0)
     assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(want)) == C.NBODY_OK
     assert lib.nbody_get_tile(0, 0, 10425, ctypes.byref(t)) == C.NBODY_OK
-    assert (t.targets_per_lane, t.waves, t.chunks) == (4, 2, 7)
-    assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(3, 1, 1))) == C.NBODY_EINVAL
-    assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(1, 1, 65))) == C.NBODY_EINVAL
-    assert lib.nbody_set_tile(1, 0, 100, ctypes.byref(C.Tile(4, 1, 1))) == C.NBODY_EINVAL
+    assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == (4, 2, 7, 0)
+    assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(1, 2, 9, 1))) == C.NBODY_OK
+    assert lib.nbody_get_tile(0, 0, 10425, ctypes.byref(t)) == C.NBODY_OK
+    assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == (1, 2, 9, 1)
+    assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(1, 2, 9, 2))) == C.NBODY_EINVAL
+    assert lib.nbody_set_tile(1, 0, 100, ctypes.byref(C.Tile(1, 1, 1, 1))) == C.NBODY_EINVAL
+    assert lib.nbody_set_tile(2, 0, 0, ctypes.byref(C.Tile(2, 1, 16, 1))) == C.NBODY_OK
+    assert lib.nbody_get_tile(2, 0, 0, ctypes.byref(t)) == C.NBODY_OK and t.variant == 1
+    assert lib.nbody_set_tile(3, 0, 10, ctypes.byref(C.Tile(1, 1, 1, 0))) == C.NBODY_EINVAL
+    assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(3, 1, 1, 0))) == C.NBODY_EINVAL
+    assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(1, 1, 65, 0))) == C.NBODY_EINVAL
+    assert lib.nbody_set_tile(1, 0, 100, ctypes.byref(C.Tile(4, 1, 1, 0))) == C.NBODY_EINVAL
     lib.nbody_reset_caches()
 
 

@@ -47,7 +47,9 @@ def _fresh_tiles():
 # ---------------------------------------------------------------------------
 # Eq. (1)
 
-TILES = [(1, 1, 1), (2, 1, 3), (4, 1, 2), (1, 2, 5), (2, 4, 2), (4, 8, 1), (1, 8, 64), (4, 2, 9)]
+TILES = [(1, 1, 1, 0), (2, 1, 3, 0), (4, 1, 2, 0), (1, 2, 5, 0), (2, 4, 2, 0), (4, 8, 1, 0),
+         (1, 8, 64, 0), (4, 2, 9, 0), (1, 1, 1, 1), (2, 1, 3, 1), (4, 2, 5, 1), (1, 4, 7, 1),
+         (2, 8, 2, 1), (1, 2, 64, 1)]
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 131, 257, 1000, 2049])
@@ -61,6 +63,20 @@ def test_accel_fp64_shapes(n):
         e = rel(got, ref)
         log(f"n={n} tile={tile} rel={e:.2e}")
         assert e <= 1e-13
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("n", [3, 200, 1031])
+def test_accel_split_shapes(n, variant):
+    """Split form on ragged sizes with the class boundary inside a group/tile."""
+    s = S.solar_system(70 + n, max(n - 31, 0), n_major=min(30, n - 1))
+    ref = oracle.accel(s.pos, s.mass, s.G)
+    for tile in [(1, 1, 1), (2, 2, 3), (4, 1, 2)]:
+        nb.set_tile(0, "split", n, *tile, variant)
+        got = H(nb.accel(T(s.pos), T(s.mass), s.G, precision="split"))
+        e = rel(got, ref)
+        log(f"split n={n} tile={tile} variant={variant} rel={e:.2e}")
+        assert e <= 2e-12
 
 
 def test_accel_fp64_random_cluster():
@@ -254,9 +270,11 @@ def _small_ensemble(count=6, steps=40):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "split"])
-def test_batched_matches_oracle(precision):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_batched_matches_oracle(precision, variant):
     systems, offs, pos, vel, mass = _small_ensemble()
     steps = 40
+    nb.set_tile(2, precision, 0, 2, 1, 16, variant)
     p, v = T(pos), T(vel)
     nb.verlet_run_batched(p, v, T(mass), offs, S.G_AU_DAY_MSUN, 0.1, steps, precision=precision)
     P, V = H(p), H(v)
