@@ -146,7 +146,8 @@ int32_t nbody_get_flags(void* workspace, void* stream, int32_t clear, int32_t* f
 /* Tile shape of the force pass: targets per lane (1, 2, 4), waves per
  * workgroup (1, 2, 4, 8), source chunks (1..64) and how sources reach the
  * lanes (variant 0: staged through LDS; 1: read once per wavefront into
- * scalar registers; the adjoint pass supports variant 0 only). */
+ * scalar registers; 2: as 1, the waves of a workgroup sharing targets and
+ * splitting the sources; the adjoint pass supports variant 0 only). */
 typedef struct {
     int32_t targets_per_lane;
     int32_t waves;

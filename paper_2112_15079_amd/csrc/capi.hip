@@ -74,15 +74,24 @@ int chunk_cap(int64_t n)
     return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxChunks, c));
 }
 
-Tile heuristic_tile(int kind, int64_t n)
+// Defaults from tile sweeps on MI355X (the autotuner refines them): about
+// 8192 wavefronts in flight; scalar-operand sources for FP64 below ~3e4
+// bodies, LDS tiles with 4 targets per lane above; the split form prefers the
+// LDS tiles at every size.
+Tile heuristic_tile(int kind, int prec, int64_t n)
 {
-    if (kind == 2) return Tile{2, 1, kBatchChunkMax};   // ensemble: per-system chunks
-    Tile t;
-    t.tpl = kind == 0 ? 2 : 1;
-    t.waves = 1;
-    const int64_t tb = (n + 64 * t.waves * t.tpl - 1) / (64 * t.waves * t.tpl);
-    int64_t c = std::max<int64_t>(1, 2048 / tb);
-    c = std::min<int64_t>(c, std::max<int64_t>(1, n / 256));
+    if (kind == 2) return Tile{2, 1, kBatchChunkMax, 0};   // ensemble: per-system chunks
+    Tile t{1, 1, 1, 0};
+    if (kind == 0 && prec == NBODY_FP64) {
+        if (n < 32768) t = Tile{1, n < 4096 ? 1 : 2, 1, 1};
+        else           t = Tile{4, 1, 1, 0};
+    } else if (kind == 0) {
+        if (n >= 32768) t = Tile{2, 8, 1, 0};
+    }
+    const int64_t tpb = targets_per_block(t);
+    const int64_t tb = (n + tpb - 1) / tpb;
+    int64_t c = std::max<int64_t>(1, 8192 / (tb * t.waves));
+    c = std::min<int64_t>(c, std::max<int64_t>(1, n / (64 * t.waves)));
     t.chunks = (int)std::min<int64_t>(c, chunk_cap(n));
     return t;
 }
@@ -98,7 +107,7 @@ Tile pick_tile(int kind, int prec, int64_t n)
             return t;
         }
     }
-    return heuristic_tile(kind, n);
+    return heuristic_tile(kind, prec, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -147,7 +156,7 @@ Layout layout(int op, int64_t n, int32_t ns, int64_t steps, int64_t K, int prec)
         if (!L.offs) L.offs = a.take((size_t)(ns + 1) * sizeof(int64_t));
         // units: per system ceil(n_k/64) target blocks (the smallest tile) times
         // at most kBatchChunkMax chunks.
-        const int64_t max_units = (n / 64 + ns) * kBatchChunkMax;
+        const int64_t max_units = (n / 64 + ns) * kBatchChunkMax;   // >= any tile's unit count
         L.units = a.take((size_t)max_units * sizeof(BatchUnit));
         L.bchunks = a.take(n);
     }
@@ -726,7 +735,7 @@ std::shared_ptr<BatchPlan> batch_plan(const int64_t* offs, int32_t ns, const Til
     bp->offsets.assign(offs, offs + ns + 1);
     const int64_t n_total = offs[ns];
     bp->bchunks.resize(n_total);
-    const int64_t tb_size = 64 * (int64_t)t.waves * t.tpl;
+    const int64_t tb_size = targets_per_block(t);
     for (int32_t k = 0; k < ns; ++k) {
         const int64_t nk = offs[k + 1] - offs[k];
         const int chunks = (int)std::min<int64_t>(kBatchChunkMax,
@@ -964,22 +973,23 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
     const int waves[4] = {1, 2, 4, 8};
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 4; ++b) {
-            Tile t{tpls[a], waves[b], 1};
-            if (kind == 1 && (t.tpl > 2 || t.waves > 4)) continue;
-            const int64_t tb = (n + 64 * t.waves * t.tpl - 1) / (64 * t.waves * t.tpl);
-            std::vector<int> cs = {1};
-            for (int64_t target : {512, 1024, 2048, 3072, 4096, 6144, 8192}) {
-                const int64_t waves_per_chunk = tb * t.waves;
-                int64_t c = target / std::max<int64_t>(waves_per_chunk, 1);
-                c = std::min<int64_t>(c, chunk_cap(n));
-                c = std::min<int64_t>(c, std::max<int64_t>(1, n / (64 * t.waves)));
-                if (c >= 1) cs.push_back((int)c);
-            }
-            std::sort(cs.begin(), cs.end());
-            cs.erase(std::unique(cs.begin(), cs.end()), cs.end());
-            for (int c : cs) {
-                cands.push_back(Tile{t.tpl, t.waves, c, 0});
-                if (kind == 0) cands.push_back(Tile{t.tpl, t.waves, c, 1});
+            for (int variant = 0; variant < (kind == 0 ? 3 : 1); ++variant) {
+                Tile t{tpls[a], waves[b], 1, variant};
+                if (kind == 1 && (t.tpl > 2 || t.waves > 4)) continue;
+                if (variant != 0 && t.tpl == 4 && t.waves == 8) continue;   // register spills
+                const int64_t tpb = targets_per_block(t);
+                const int64_t tb = (n + tpb - 1) / tpb;
+                std::vector<int> cs = {1};
+                for (int64_t target : {512, 1024, 2048, 3072, 4096, 6144, 8192}) {
+                    const int64_t waves_per_chunk = tb * t.waves;
+                    int64_t c = target / std::max<int64_t>(waves_per_chunk, 1);
+                    c = std::min<int64_t>(c, chunk_cap(n));
+                    c = std::min<int64_t>(c, std::max<int64_t>(1, n / (64 * t.waves)));
+                    if (c >= 1) cs.push_back((int)c);
+                }
+                std::sort(cs.begin(), cs.end());
+                cs.erase(std::unique(cs.begin(), cs.end()), cs.end());
+                for (int c : cs) cands.push_back(Tile{t.tpl, t.waves, c, variant});
             }
         }
 

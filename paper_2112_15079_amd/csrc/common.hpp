@@ -17,13 +17,22 @@ struct Tile {
     int tpl;          // targets per lane: 1, 2, 4
     int waves;        // wavefronts per workgroup: 1, 2, 4, 8
     int chunks;       // source chunks, 1..64
-    int variant = 0;  // 0: sources staged in LDS; 1: sources as scalar operands
+    int variant = 0;  // 0: sources staged in LDS; 1: sources as scalar operands;
+                      // 2: as 1, with the waves of a group splitting the sources
 };
 
 constexpr int kMaxChunks = 64;
 
 // Source tile width (bodies staged in LDS per pass) = lanes of a workgroup.
 inline int tile_width(const Tile& t) { return 64 * t.waves; }
+
+// Targets owned by one workgroup: variants 0 and 1 spread 64*waves lanes
+// over distinct targets; in variant 2 the waves share 64*tpl targets and
+// split the sources among themselves.
+inline int64_t targets_per_block(const Tile& t)
+{
+    return (int64_t)64 * t.tpl * (t.variant == 2 ? 1 : t.waves);
+}
 
 bool tile_supported(const Tile& t);
 

@@ -320,17 +320,24 @@ __device__ __forceinline__ void kahan_flush(Kahan<T>& k, float (&bx)[T], float (
     }
 }
 
-template <int T, int W, bool SPLIT>
+// One workgroup of W wavefronts.  SHARE = false (variant 1): each wave owns
+// its own targets (lane l of the group holds tb0 + t*64*W + l, as in the LDS
+// variant) and sweeps all sources [jbeg, jend).  SHARE = true (variant 2):
+// all waves share the targets [tb0, tb0 + 64*T) (lane l holds tb0 + t*64 + l)
+// and split the sources into W contiguous runs; the W partial sums are added
+// in wave order through LDS, so one partial per group reaches global memory.
+template <int T, int W, bool SPLIT, bool SHARE>
 __device__ __forceinline__ void force_block_s(const double* __restrict__ pos,
                                               const double* __restrict__ gm, int64_t stride,
                                               int64_t n, int64_t n_major, int64_t tb0,
                                               int64_t jbeg, int64_t jend,
                                               double* __restrict__ part_c)
 {
-    constexpr int NT = 64 * W;
-    const int tid = threadIdx.x;
+    constexpr int TS = SHARE ? 64 : 64 * W;   // stride between a lane's targets
+    const int lane = SHARE ? (threadIdx.x & 63) : threadIdx.x;
+    const int wave = SHARE ? (threadIdx.x >> 6) : 0;
     Targets<T> tg;
-    load_targets<T, NT>(tg, pos, stride, n, tb0, tid);
+    load_targets<T, TS>(tg, pos, stride, n, tb0, lane);
     double ax[T], ay[T], az[T];
     Kahan<T> k;
     float bx[T], by[T], bz[T];
@@ -342,13 +349,21 @@ __device__ __forceinline__ void force_block_s(const double* __restrict__ pos,
         bx[t] = 0.f; by[t] = 0.f; bz[t] = 0.f;
     }
     const PolyConst c32 = {vreg_const(1.875), vreg_const(1.5)};
-    const int64_t tend = tb0 + (int64_t)NT * T;
+    const int64_t tend = tb0 + (int64_t)TS * T;
     const double* __restrict__ px = pos;
     const double* __restrict__ py = pos + stride;
     const double* __restrict__ pz = pos + 2 * stride;
+
+    // this wave's run of sources (a multiple of kSGroup long, except the last)
+    constexpr int NW = SHARE ? W : 1;
+    const int64_t span = jend - jbeg;
+    const int64_t run = ((span + NW - 1) / NW + kSGroup - 1) / kSGroup * kSGroup;
+    const int64_t wb = jbeg + (int64_t)wave * run;
+    const int64_t we = (wb + run < jend) ? wb + run : jend;
+
     int small_groups = 0;
-    int64_t j = jbeg;
-    for (; j + kSGroup <= jend; j += kSGroup) {
+    int64_t j = wb;
+    for (; j + kSGroup <= we; j += kSGroup) {
         double xs[kSGroup], ys[kSGroup], zs[kSGroup], gs[kSGroup];
 #pragma unroll
         for (int u = 0; u < kSGroup; ++u) {
@@ -392,48 +407,68 @@ __device__ __forceinline__ void force_block_s(const double* __restrict__ pos,
             }
         }
     }
-    for (; j < jend; ++j) {
+    for (; j < we; ++j) {
         const double sx = px[j], sy = py[j], sz = pz[j], sg = gm[j];
         if (!SPLIT || j < n_major)
             pair_f64<T, true, SPLIT>(sx, sy, sz, sg, j, tg, ax, ay, az, c32);
         else
             pair_small<T, true>(sx, sy, sz, sg, j, tg, bx, by, bz);
     }
-    if (SPLIT) kahan_flush(k, bx, by, bz);
-
+    if (SPLIT) {
+        kahan_flush(k, bx, by, bz);
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-        const int64_t p = tb0 + (int64_t)t * NT + tid;
-        if (p < n) {
-            double vx = ax[t], vy = ay[t], vz = az[t];
-            if (SPLIT) {
-                vx += (double)k.sx[t] - (double)k.cx[t];
-                vy += (double)k.sy[t] - (double)k.cy[t];
-                vz += (double)k.sz[t] - (double)k.cz[t];
+        for (int t = 0; t < T; ++t) {
+            ax[t] += (double)k.sx[t] - (double)k.cx[t];
+            ay[t] += (double)k.sy[t] - (double)k.cy[t];
+            az[t] += (double)k.sz[t] - (double)k.cz[t];
+        }
+    }
+
+    if (SHARE && W > 1) {
+        __shared__ double red[W][3 * T][64];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            red[wave][3 * t + 0][lane] = ax[t];
+            red[wave][3 * t + 1][lane] = ay[t];
+            red[wave][3 * t + 2][lane] = az[t];
+        }
+        __syncthreads();
+        // wave w finishes component rows w, w + W, ...; waves summed in order
+        for (int row = wave; row < 3 * T; row += W) {
+            double s = red[0][row][lane];
+            for (int w = 1; w < W; ++w) s += red[w][row][lane];
+            const int t = row / 3, comp = row % 3;
+            const int64_t p = tb0 + (int64_t)t * 64 + lane;
+            if (p < n) part_c[comp * stride + p] = s;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int64_t p = tb0 + (int64_t)t * TS + lane;
+            if (p < n) {
+                part_c[p] = ax[t];
+                part_c[stride + p] = ay[t];
+                part_c[2 * stride + p] = az[t];
             }
-            part_c[p] = vx;
-            part_c[stride + p] = vy;
-            part_c[2 * stride + p] = vz;
         }
     }
 }
 
-template <int T, int W, bool SPLIT>
+template <int T, int W, bool SPLIT, bool SHARE>
 __global__ __launch_bounds__(64 * W) void k_force_s(const double* __restrict__ pos,
                                                     const double* __restrict__ gm, int64_t n,
                                                     const int64_t* __restrict__ nmaj,
                                                     int64_t chunk_len, double* __restrict__ part)
 {
-    constexpr int NT = 64 * W;
     const int64_t n_major = SPLIT ? nmaj[0] : 0;
-    const int64_t tb0 = (int64_t)blockIdx.x * NT * T;
+    const int64_t tb0 = (int64_t)blockIdx.x * (SHARE ? 64 : 64 * W) * T;
     const int64_t c = blockIdx.y;
     const int64_t jbeg = c * chunk_len;
     const int64_t jend = (jbeg + chunk_len < n) ? jbeg + chunk_len : n;
-    force_block_s<T, W, SPLIT>(pos, gm, n, n, n_major, tb0, jbeg, jend, part + c * 3 * n);
+    force_block_s<T, W, SPLIT, SHARE>(pos, gm, n, n, n_major, tb0, jbeg, jend, part + c * 3 * n);
 }
 
-template <int T, int W, bool SPLIT>
+template <int T, int W, bool SPLIT, bool SHARE>
 __global__ __launch_bounds__(64 * W) void k_force_s_batched(const double* __restrict__ pos,
                                                             const double* __restrict__ gm,
                                                             int64_t n_total,
@@ -442,17 +477,19 @@ __global__ __launch_bounds__(64 * W) void k_force_s_batched(const double* __rest
                                                             const int64_t* __restrict__ nmaj,
                                                             double* __restrict__ part)
 {
-    constexpr int NT = 64 * W;
+    constexpr int GR = SHARE ? kSGroup * W : kSGroup;
     for (int64_t u = blockIdx.x; u < num_units; u += gridDim.x) {
         const BatchUnit w = units[u];
         const int64_t n_major = SPLIT ? nmaj[w.sys] : 0;
         const int64_t n = w.n;
-        const int64_t chunk_len = ((n + w.chunks - 1) / w.chunks + NT - 1) / NT * NT;
+        const int64_t chunk_len = ((n + w.chunks - 1) / w.chunks + GR - 1) / GR * GR;
         const int64_t jbeg = (int64_t)w.chunk * chunk_len;
         const int64_t jend = (jbeg + chunk_len < n) ? jbeg + chunk_len : n;
-        const int64_t tb0 = (int64_t)w.tblock * NT * T;
-        force_block_s<T, W, SPLIT>(pos + w.body0, gm + w.body0, n_total, n, n_major, tb0, jbeg,
-                                   jend, part + (int64_t)w.chunk * 3 * n_total + w.body0);
+        const int64_t tb0 = (int64_t)w.tblock * (SHARE ? 64 : 64 * W) * T;
+        force_block_s<T, W, SPLIT, SHARE>(pos + w.body0, gm + w.body0, n_total, n, n_major, tb0,
+                                          jbeg, jend,
+                                          part + (int64_t)w.chunk * 3 * n_total + w.body0);
+        if (SHARE && W > 1) __syncthreads();   // the LDS reduction buffer is reused
     }
 }
 
@@ -507,12 +544,13 @@ bool tile_supported(const Tile& t)
     const bool tpl_ok = t.tpl == 1 || t.tpl == 2 || t.tpl == 4;
     const bool w_ok = t.waves == 1 || t.waves == 2 || t.waves == 4 || t.waves == 8;
     return tpl_ok && w_ok && t.chunks >= 1 && t.chunks <= kMaxChunks &&
-           (t.variant == 0 || t.variant == 1);
+           (t.variant >= 0 && t.variant <= 2);
 }
 
 int64_t chunk_length(int64_t n, const Tile& t)
 {
-    const int64_t tw = tile_width(t);
+    const int64_t tw = t.variant == 2 ? (int64_t)kSGroup * t.waves
+                     : t.variant == 1 ? (int64_t)kSGroup : tile_width(t);
     const int64_t per = (n + t.chunks - 1) / t.chunks;
     return (per + tw - 1) / tw * tw;
 }
@@ -523,16 +561,24 @@ static hipError_t launch_tw(int precision, int variant, const double* pos, const
                             int64_t chunk_len, int chunks, double* part, hipStream_t s)
 {
     constexpr int NT = 64 * W;
-    const dim3 grid((unsigned)((n + (int64_t)NT * T - 1) / ((int64_t)NT * T)), (unsigned)chunks);
-    if (variant == 1) {
-        if (precision == 0)
-            hipLaunchKernelGGL((k_force_s<T, W, false>), grid, dim3(NT), 0, s, pos, gm, n, nmaj,
-                               chunk_len, part);
+    if (variant == 1 || variant == 2) {
+        const int64_t tpb = (variant == 2 ? 64 : NT) * T;
+        const dim3 g1((unsigned)((n + tpb - 1) / tpb), (unsigned)chunks);
+        if (variant == 1 && precision == 0)
+            hipLaunchKernelGGL((k_force_s<T, W, false, false>), g1, dim3(NT), 0, s, pos, gm, n,
+                               nmaj, chunk_len, part);
+        else if (variant == 1)
+            hipLaunchKernelGGL((k_force_s<T, W, true, false>), g1, dim3(NT), 0, s, pos, gm, n,
+                               nmaj, chunk_len, part);
+        else if (precision == 0)
+            hipLaunchKernelGGL((k_force_s<T, W, false, true>), g1, dim3(NT), 0, s, pos, gm, n,
+                               nmaj, chunk_len, part);
         else
-            hipLaunchKernelGGL((k_force_s<T, W, true>), grid, dim3(NT), 0, s, pos, gm, n, nmaj,
-                               chunk_len, part);
+            hipLaunchKernelGGL((k_force_s<T, W, true, true>), g1, dim3(NT), 0, s, pos, gm, n,
+                               nmaj, chunk_len, part);
         return hipGetLastError();
     }
+    const dim3 grid((unsigned)((n + (int64_t)NT * T - 1) / ((int64_t)NT * T)), (unsigned)chunks);
     if (precision == 0)
         hipLaunchKernelGGL((k_force<T, W, false>), grid, dim3(NT), 0, s, pos, mass, n, nmaj,
                            chunk_len, G, part);
@@ -549,13 +595,19 @@ static hipError_t launch_batched_tw(int precision, int variant, const double* po
                                     const int64_t* nmaj, int grid, double* part, hipStream_t s)
 {
     constexpr int NT = 64 * W;
-    if (variant == 1) {
-        if (precision == 0)
-            hipLaunchKernelGGL((k_force_s_batched<T, W, false>), dim3(grid), dim3(NT), 0, s, pos,
-                               gm, n_total, units, num_units, nmaj, part);
+    if (variant == 1 || variant == 2) {
+        if (variant == 1 && precision == 0)
+            hipLaunchKernelGGL((k_force_s_batched<T, W, false, false>), dim3(grid), dim3(NT), 0, s,
+                               pos, gm, n_total, units, num_units, nmaj, part);
+        else if (variant == 1)
+            hipLaunchKernelGGL((k_force_s_batched<T, W, true, false>), dim3(grid), dim3(NT), 0, s,
+                               pos, gm, n_total, units, num_units, nmaj, part);
+        else if (precision == 0)
+            hipLaunchKernelGGL((k_force_s_batched<T, W, false, true>), dim3(grid), dim3(NT), 0, s,
+                               pos, gm, n_total, units, num_units, nmaj, part);
         else
-            hipLaunchKernelGGL((k_force_s_batched<T, W, true>), dim3(grid), dim3(NT), 0, s, pos,
-                               gm, n_total, units, num_units, nmaj, part);
+            hipLaunchKernelGGL((k_force_s_batched<T, W, true, true>), dim3(grid), dim3(NT), 0, s,
+                               pos, gm, n_total, units, num_units, nmaj, part);
         return hipGetLastError();
     }
     if (precision == 0)
@@ -580,7 +632,7 @@ hipError_t launch_force(int precision, const Tile& tile, const double* pos, cons
                         const double* gm, int64_t n, const int64_t* nmaj, double G, double* part,
                         hipStream_t s)
 {
-    if (tile.variant == 1 && !gm) return hipErrorInvalidValue;
+    if (tile.variant != 0 && !gm) return hipErrorInvalidValue;
     const int64_t L = chunk_length(n, tile);
     const int chunks = effective_chunks(n, tile);
 #define NB_CASE(TT, WW)                                                                  \
@@ -597,7 +649,7 @@ hipError_t launch_force_batched(int precision, const Tile& tile, const double* p
                                 const BatchUnit* units, int64_t num_units, const int64_t* nmaj,
                                 int grid, double* part, hipStream_t s)
 {
-    if (tile.variant == 1 && !gm) return hipErrorInvalidValue;
+    if (tile.variant != 0 && !gm) return hipErrorInvalidValue;
 #define NB_CASE(TT, WW)                                                                   \
     if (tile.tpl == TT && tile.waves == WW)                                               \
         return launch_batched_tw<TT, WW>(precision, tile.variant, pos, mass, gm, n_total, G, \

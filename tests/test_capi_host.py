@@ -136,7 +136,7 @@ def test_tile_table():
     assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(1, 2, 9, 1))) == C.NBODY_OK
     assert lib.nbody_get_tile(0, 0, 10425, ctypes.byref(t)) == C.NBODY_OK
     assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == (1, 2, 9, 1)
-    assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(1, 2, 9, 2))) == C.NBODY_EINVAL
+    assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(1, 2, 9, 3))) == C.NBODY_EINVAL
     assert lib.nbody_set_tile(1, 0, 100, ctypes.byref(C.Tile(1, 1, 1, 1))) == C.NBODY_EINVAL
     assert lib.nbody_set_tile(2, 0, 0, ctypes.byref(C.Tile(2, 1, 16, 1))) == C.NBODY_OK
     assert lib.nbody_get_tile(2, 0, 0, ctypes.byref(t)) == C.NBODY_OK and t.variant == 1

@@ -49,7 +49,7 @@ def _fresh_tiles():
 
 TILES = [(1, 1, 1, 0), (2, 1, 3, 0), (4, 1, 2, 0), (1, 2, 5, 0), (2, 4, 2, 0), (4, 8, 1, 0),
          (1, 8, 64, 0), (4, 2, 9, 0), (1, 1, 1, 1), (2, 1, 3, 1), (4, 2, 5, 1), (1, 4, 7, 1),
-         (2, 8, 2, 1), (1, 2, 64, 1)]
+         (2, 8, 2, 1), (1, 2, 64, 1), (1, 2, 1, 2), (2, 4, 3, 2), (4, 2, 5, 2), (1, 8, 9, 2)]
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 131, 257, 1000, 2049])
@@ -65,7 +65,7 @@ def test_accel_fp64_shapes(n):
         assert e <= 1e-13
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("n", [3, 200, 1031])
 def test_accel_split_shapes(n, variant):
     """Split form on ragged sizes with the class boundary inside a group/tile."""
@@ -270,11 +270,11 @@ def _small_ensemble(count=6, steps=40):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "split"])
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_batched_matches_oracle(precision, variant):
     systems, offs, pos, vel, mass = _small_ensemble()
     steps = 40
-    nb.set_tile(2, precision, 0, 2, 1, 16, variant)
+    nb.set_tile(2, precision, 0, 2, 4 if variant == 2 else 1, 16, variant)
     p, v = T(pos), T(vel)
     nb.verlet_run_batched(p, v, T(mass), offs, S.G_AU_DAY_MSUN, 0.1, steps, precision=precision)
     P, V = H(p), H(v)
