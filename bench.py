@@ -269,6 +269,10 @@ def bench_ensemble(args, S, nb, torch, np, dev):
            "config": {"workload": "512 systems: Sun, 30 majors, U{100..8192} asteroids, seeds 100..611",
                       "bodies": int(offs[-1]), "pairs_per_step": pairs}}
     for prec in ("fp64", "split"):
+        if not args.no_tune:
+            tile, ms = nb.autotune_batched(pos0, m, offs, G, prec)
+            log(f"autotune ensemble {prec}: {tile} {ms:.3f} ms per force pass")
+            out.setdefault("tiles", {})[prec] = tile
         p, v = pos0.clone(), vel0.clone()
         nb.verlet_run_batched(p, v, m, offs, G, dt, W, precision=prec)
         torch.cuda.synchronize()

@@ -174,6 +174,15 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
                        void* workspace, size_t workspace_bytes, void* stream,
                        nbody_tile* best_host, double* best_ms_host);
 
+/* As nbody_autotune for the batched ensemble: times the ensemble's force pass
+ * (one launch over all systems' work units) for candidate tile shapes and
+ * keeps the fastest for kind 2.  offsets_host as for nbody_verlet_run_batched.
+ * Synchronises `stream`. */
+int32_t nbody_autotune_batched(int32_t precision, const double* pos, const double* mass,
+                               const int64_t* offsets_host, int32_t num_systems, double G,
+                               double small_mass, void* workspace, size_t workspace_bytes,
+                               void* stream, nbody_tile* best_host, double* best_ms_host);
+
 /* Average duration (ms) of one force pass (kind 0: Eq. (1) for `precision`;
  * kind 1: the adjoint's transpose-Jacobian pass) over `reps` back-to-back
  * launches with the current tile shape, timed by HIP events recorded on

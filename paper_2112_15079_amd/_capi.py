@@ -23,7 +23,8 @@ OP_ACCEL, OP_RUN, OP_ADJOINT, OP_BATCHED, OP_ENERGY = range(5)
 EXPORTS = (
     "nbody_workspace_bytes", "nbody_accel", "nbody_verlet_run", "nbody_verlet_adjoint",
     "nbody_verlet_run_batched", "nbody_energy", "nbody_momenta", "nbody_get_flags",
-    "nbody_get_tile", "nbody_set_tile", "nbody_autotune", "nbody_time_force", "nbody_reset_caches",
+    "nbody_get_tile", "nbody_set_tile", "nbody_autotune", "nbody_autotune_batched",
+    "nbody_time_force", "nbody_reset_caches",
     "nbody_last_error", "nbody_version",
 )
 
@@ -87,6 +88,9 @@ def load():
         lib.nbody_autotune.restype = _I32
         lib.nbody_autotune.argtypes = [_I32, _I32, _P, _P, _I64, _D, _D, _P, _SZ, _P,
                                        ctypes.POINTER(Tile), ctypes.POINTER(_D)]
+        lib.nbody_autotune_batched.restype = _I32
+        lib.nbody_autotune_batched.argtypes = [_I32, _P, _P, _P, _I32, _D, _D, _P, _SZ, _P,
+                                               ctypes.POINTER(Tile), ctypes.POINTER(_D)]
         lib.nbody_time_force.restype = _I32
         lib.nbody_time_force.argtypes = [_I32, _I32, _P, _P, _I64, _D, _D, _I32, _P, _SZ, _P,
                                          ctypes.POINTER(_D)]

@@ -778,62 +778,110 @@ int device_cus(int* cus)
 
 extern "C" {
 
+}  // extern "C"
+
+namespace {
+
+int check_offsets(const int64_t* offsets_host, int32_t num_systems)
+{
+    if (!offsets_host || num_systems < 1) return fail(NBODY_EINVAL, "need offsets and >= 1 system");
+    if (offsets_host[0] != 0) return fail(NBODY_EINVAL, "offsets[0] must be 0");
+    for (int32_t k = 0; k < num_systems; ++k) {
+        if (offsets_host[k + 1] <= offsets_host[k])
+            return fail(NBODY_EINVAL, "system %d is empty or offsets decrease", k);
+        if (offsets_host[k + 1] - offsets_host[k] > ((int64_t)1 << 24))
+            return fail(NBODY_EUNSUPPORTED, "system %d has more than 2^24 bodies", k);
+    }
+    return NBODY_OK;
+}
+
+// Uploads the ensemble's work list for tile t and fills the batched fields of P.
+int batched_plan_upload(const int64_t* offsets_host, int32_t ns, const Tile& t, void* ws,
+                        const Layout& L, hipStream_t s, StepPlan* P)
+{
+    const auto bp = batch_plan(offsets_host, ns, t);
+    const int64_t n = offsets_host[ns];
+    BatchUnit* units = at<BatchUnit>(ws, L.units);
+    int8_t* bchunks = at<int8_t>(ws, L.bchunks);
+    NB_HIP(hipMemcpyAsync(units, bp->units.data(), bp->units.size() * sizeof(BatchUnit),
+                          hipMemcpyHostToDevice, s));
+    NB_HIP(hipMemcpyAsync(bchunks, bp->bchunks.data(), n, hipMemcpyHostToDevice, s));
+    int cus = 0;
+    NB_TRY(device_cus(&cus));
+    P->tile = t;
+    P->units = units;
+    P->num_units = (int64_t)bp->units.size();
+    P->grid = (int)std::min<int64_t>(P->num_units, (int64_t)cus * (16 / t.waves));
+    P->bchunks = bchunks;
+    return NBODY_OK;
+}
+
+// Class order of the ensemble (split form): partition, gathers and G m.
+int batched_split_prepare(const double* pos, const double* vel, const double* mass,
+                          const int64_t* offsets_host, int32_t ns, double G, double small_mass,
+                          void* ws, const Layout& L, hipStream_t s, StepPlan* P)
+{
+    const int64_t n = offsets_host[ns];
+    int64_t* offs = at<int64_t>(ws, L.offs);
+    NB_HIP(hipMemcpyAsync(offs, offsets_host, (ns + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    NB_HIP(hipStreamSynchronize(s));   // offsets_host may be released by the caller on return
+    NB_HIP(launch_partition(mass, offs, ns, 0, small_mass, at<int32_t>(ws, L.perm),
+                            at<int64_t>(ws, L.nmaj), s));
+    const int32_t* perm = at<int32_t>(ws, L.perm);
+    double* pos_c = at<double>(ws, L.pos_c);
+    double* vel_c = at<double>(ws, L.vel_c);
+    double* mass_c = at<double>(ws, L.mass_c);
+    double* gm = at<double>(ws, L.gm);
+    NB_HIP(launch_gather(perm, n, pos, pos_c, 3, s));
+    if (vel) NB_HIP(launch_gather(perm, n, vel, vel_c, 3, s));
+    NB_HIP(launch_gather(perm, n, mass, mass_c, 1, s));
+    NB_HIP(launch_scale(mass_c, G, n, gm, s));
+    P->mass = mass_c;
+    P->gm = gm;
+    P->vel = vel_c;
+    P->buf[0] = pos_c;
+    P->buf[1] = at<double>(ws, L.alt_c);
+    P->nmaj = at<int64_t>(ws, L.nmaj);
+    return NBODY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int32_t nbody_verlet_run_batched(double* pos, double* vel, const double* mass,
                                  const int64_t* offsets_host, int32_t num_systems, double G,
                                  double dt, int64_t steps, int32_t precision, double small_mass,
                                  void* workspace, size_t workspace_bytes, void* stream)
 {
     g_err.clear();
-    if (!offsets_host || num_systems < 1) return fail(NBODY_EINVAL, "need offsets and >= 1 system");
-    if (offsets_host[0] != 0) return fail(NBODY_EINVAL, "offsets[0] must be 0");
-    for (int32_t k = 0; k < num_systems; ++k)
-        if (offsets_host[k + 1] <= offsets_host[k])
-            return fail(NBODY_EINVAL, "system %d is empty or offsets decrease", k);
+    NB_TRY(check_offsets(offsets_host, num_systems));
     const int64_t n = offsets_host[num_systems];
     NB_TRY(check_common(pos, mass, n, G));
     NB_TRY(check_prec(precision, small_mass));
     if (!vel) return fail(NBODY_EINVAL, "vel is NULL");
     if (steps < 0) return fail(NBODY_EINVAL, "steps must be >= 0");
     if (!std::isfinite(dt)) return fail(NBODY_EINVAL, "dt is not finite");
-    for (int32_t k = 0; k < num_systems; ++k)
-        if (offsets_host[k + 1] - offsets_host[k] > ((int64_t)1 << 24))
-            return fail(NBODY_EUNSUPPORTED, "system %d has more than 2^24 bodies", k);
     const Layout L = layout(NBODY_OP_BATCHED, n, num_systems, steps, 1, precision);
     NB_TRY(check_ws(workspace, workspace_bytes, L.total));
     if (steps == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
 
-    Tile t = pick_tile(2, precision, 0);
-    const auto bp = batch_plan(offsets_host, num_systems, t);
-    BatchUnit* units = at<BatchUnit>(workspace, L.units);
-    int8_t* bchunks = at<int8_t>(workspace, L.bchunks);
-    int64_t* offs = at<int64_t>(workspace, L.offs);
-    NB_HIP(hipMemcpyAsync(units, bp->units.data(), bp->units.size() * sizeof(BatchUnit),
-                          hipMemcpyHostToDevice, s));
-    NB_HIP(hipMemcpyAsync(bchunks, bp->bchunks.data(), n, hipMemcpyHostToDevice, s));
-    NB_HIP(hipMemcpyAsync(offs, bp->offsets.data(), (num_systems + 1) * sizeof(int64_t),
-                          hipMemcpyHostToDevice, s));
-    int cus = 0;
-    NB_TRY(device_cus(&cus));
-
     StepPlan P;
     P.prec = precision;
-    P.tile = t;
     P.chunks = 0;
     P.n = n;
     P.G = G;
     P.dt = dt;
     P.part = at<double>(workspace, L.part);
     P.flags = at<uint32_t>(workspace, L.flags);
-    P.units = units;
-    P.num_units = (int64_t)bp->units.size();
-    P.grid = (int)std::min<int64_t>(P.num_units, (int64_t)cus * (16 / t.waves));
-    P.bchunks = bchunks;
-    double* alt = at<double>(workspace, L.alt);
-    double* gm = at<double>(workspace, L.gm);
-    P.gm = gm;
+    NB_TRY(batched_plan_upload(offsets_host, num_systems, pick_tile(2, precision, 0), workspace, L,
+                               s, &P));
     if (precision == NBODY_FP64) {
+        double* alt = at<double>(workspace, L.alt);
+        double* gm = at<double>(workspace, L.gm);
         P.mass = mass;
+        P.gm = gm;
         P.vel = vel;
         NB_HIP(launch_scale(mass, G, n, gm, s));
         if (steps & 1) {
@@ -846,25 +894,88 @@ int32_t nbody_verlet_run_batched(double* pos, double* vel, const double* mass,
         }
         return run_steps(P, steps, s, true);
     }
-    NB_HIP(launch_partition(mass, offs, num_systems, 0, small_mass, at<int32_t>(workspace, L.perm),
-                            at<int64_t>(workspace, L.nmaj), s));
+    NB_TRY(batched_split_prepare(pos, vel, mass, offsets_host, num_systems, G, small_mass,
+                                 workspace, L, s, &P));
     const int32_t* perm = at<int32_t>(workspace, L.perm);
-    double* pos_c = at<double>(workspace, L.pos_c);
-    double* vel_c = at<double>(workspace, L.vel_c);
-    double* mass_c = at<double>(workspace, L.mass_c);
-    double* alt_c = at<double>(workspace, L.alt_c);
-    NB_HIP(launch_gather(perm, n, pos, pos_c, 3, s));
-    NB_HIP(launch_gather(perm, n, vel, vel_c, 3, s));
-    NB_HIP(launch_gather(perm, n, mass, mass_c, 1, s));
-    NB_HIP(launch_scale(mass_c, G, n, gm, s));
-    P.mass = mass_c;
-    P.vel = vel_c;
-    P.buf[0] = pos_c;
-    P.buf[1] = alt_c;
-    P.nmaj = at<int64_t>(workspace, L.nmaj);
     NB_TRY(run_steps(P, steps, s, true));
     NB_HIP(launch_scatter(perm, n, P.buf[steps & 1], pos, 3, s));
-    NB_HIP(launch_scatter(perm, n, vel_c, vel, 3, s));
+    NB_HIP(launch_scatter(perm, n, P.vel, vel, 3, s));
+    return NBODY_OK;
+}
+
+int32_t nbody_autotune_batched(int32_t precision, const double* pos, const double* mass,
+                               const int64_t* offsets_host, int32_t num_systems, double G,
+                               double small_mass, void* workspace, size_t workspace_bytes,
+                               void* stream, nbody_tile* best_host, double* best_ms_host)
+{
+    g_err.clear();
+    NB_TRY(check_offsets(offsets_host, num_systems));
+    const int64_t n = offsets_host[num_systems];
+    NB_TRY(check_common(pos, mass, n, G));
+    NB_TRY(check_prec(precision, small_mass));
+    const Layout L = layout(NBODY_OP_BATCHED, n, num_systems, 1, 1, precision);
+    NB_TRY(check_ws(workspace, workspace_bytes, L.total));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    StepPlan P;
+    P.prec = precision;
+    P.n = n;
+    P.G = G;
+    P.part = at<double>(workspace, L.part);
+    const double* pos_w = pos;
+    if (precision == NBODY_FP64) {
+        double* gm = at<double>(workspace, L.gm);
+        P.mass = mass;
+        P.gm = gm;
+        NB_HIP(launch_scale(mass, G, n, gm, s));
+    } else {
+        NB_TRY(batched_split_prepare(pos, nullptr, mass, offsets_host, num_systems, G, small_mass,
+                                     workspace, L, s, &P));
+        pos_w = P.buf[0];
+    }
+    std::vector<Tile> cands;
+    for (int tpl : {1, 2, 4})
+        for (int w : {1, 2, 4})
+            for (int v = 0; v < 3; ++v) cands.push_back(Tile{tpl, w, kBatchChunkMax, v});
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    NB_HIP(hipEventCreate(&e0));
+    NB_HIP(hipEventCreate(&e1));
+    Tile best = cands.front();
+    float best_ms = 1e30f;
+    int status = NBODY_OK;
+    for (const Tile& t : cands) {
+        if ((status = batched_plan_upload(offsets_host, num_systems, t, workspace, L, s, &P)) != NBODY_OK)
+            break;
+        const int reps = 3;
+        if ((status = force(P, pos_w, s)) != NBODY_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { status = fail(NBODY_EHIP, "event record"); break; }
+        for (int r = 0; r < reps && status == NBODY_OK; ++r) status = force(P, pos_w, s);
+        if (status != NBODY_OK) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            status = fail(NBODY_EHIP, "event sync");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status != NBODY_OK) return status;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_tiles[std::make_tuple(2, (int)precision, size_class(0))] = best;
+    }
+    if (best_host) {
+        best_host->targets_per_lane = best.tpl;
+        best_host->waves = best.waves;
+        best_host->chunks = best.chunks;
+        best_host->variant = best.variant;
+    }
+    if (best_ms_host) *best_ms_host = best_ms;
     return NBODY_OK;
 }
 

@@ -89,16 +89,22 @@ __device__ __forceinline__ void load_targets(Targets<T>& tg, const double* __res
     }
 }
 
+// Light sources of the split form (j >= small_from) carry G m as an FP32
+// value in the low half of the gm slot (see small_gm), saving a conversion
+// per pair in the FP32 sweep.
 __device__ __forceinline__ Src load_source(const double* __restrict__ pos,
                                            const double* __restrict__ mass, int64_t stride,
-                                           int64_t j, int64_t jend, double G)
+                                           int64_t j, int64_t jend, double G,
+                                           int64_t small_from = INT64_MAX)
 {
     Src s;
     if (j < jend) {
         s.x = pos[j];
         s.y = pos[stride + j];
         s.z = pos[2 * stride + j];
-        s.gm = G * mass[j];
+        const double gm = G * mass[j];
+        s.gm = j < small_from ? gm
+                              : __builtin_bit_cast(double, (uint64_t)__builtin_bit_cast(uint32_t, (float)gm));
     } else {
         s.x = kPad;
         s.y = kPad;
@@ -151,6 +157,11 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x)
     s = t;
 }
 
+__device__ __forceinline__ float small_gm(double slot)
+{
+    return __builtin_bit_cast(float, (uint32_t)__builtin_bit_cast(uint64_t, slot));
+}
+
 template <int T, bool MASK>
 __device__ __forceinline__ void sweep_small(const Src* __restrict__ tile, int jb, int je, int j0,
                                             const Targets<T>& tg, Kahan<T>& k)
@@ -163,7 +174,7 @@ __device__ __forceinline__ void sweep_small(const Src* __restrict__ tile, int jb
 #pragma unroll 4
         for (int jj = b0; jj < b1; ++jj) {
             const Src s = tile[jj];
-            const float gm = (float)s.gm;
+            const float gm = small_gm(s.gm);
 #pragma unroll
             for (int t = 0; t < T; ++t) {
                 const float dx = (float)(s.x - tg.x[t]);
@@ -214,12 +225,14 @@ __device__ __forceinline__ void force_block(const double* __restrict__ pos,
     const int64_t tend = tb0 + (int64_t)NT * T;
     const PolyConst c32 = {vreg_const(1.875), vreg_const(1.5)};
 
-    Src next = load_source(pos, mass, stride, jbeg + tid, jend, G);
+    const int64_t small_from = SPLIT ? n_major : INT64_MAX;
+    Src next = load_source(pos, mass, stride, jbeg + tid, jend, G, small_from);
     for (int64_t j0 = jbeg; j0 < jend; j0 += NT) {
         __syncthreads();
         tile[tid] = next;
         __syncthreads();
-        if (j0 + NT < jend) next = load_source(pos, mass, stride, j0 + NT + tid, jend, G);
+        if (j0 + NT < jend)
+            next = load_source(pos, mass, stride, j0 + NT + tid, jend, G, small_from);
         const bool diag = (j0 < tend) && (tb0 < j0 + NT);
         const int j0i = (int)j0;
         if (!SPLIT) {

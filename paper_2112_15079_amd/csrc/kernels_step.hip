@@ -14,11 +14,13 @@ constexpr int kBlock = 256;
 //   kOpen:  v += dt/2 a;  r_out = r_in + dt v   (v_{i+3/2}, r_{i+2})
 // Eqs. (3)-(4) follow: r_{i+1} = r_i + dt (v_i + dt/2 a_i) and
 // v_{i+1} = v_i + dt/2 a_i + dt/2 a_{i+1}.
-// One thread per (body, component): the partial loads of a batch are issued
-// together and then added in chunk order, so the sum is the same for any
-// batch size while the loads overlap.
-constexpr int kLoadBatch = 16;
+// GS threads per (body, component): thread `sub` of a group adds chunks
+// sub, sub + GS, ... in ascending order with its loads batched, then lane 0
+// of the group adds the GS sub-sums in sub order.  The order is fixed, so the
+// result is deterministic, and the loads of all groups overlap.
+constexpr int kLoadBatch = 8;
 
+template <int GS>
 __global__ __launch_bounds__(kBlock) void k_step(const double* __restrict__ part, int chunks,
                                                  const int8_t* __restrict__ body_chunks,
                                                  int64_t n, double* __restrict__ vel,
@@ -27,21 +29,39 @@ __global__ __launch_bounds__(kBlock) void k_step(const double* __restrict__ part
                                                  double* __restrict__ acc, double hdt, double dt,
                                                  int mode, uint32_t* __restrict__ flags)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;   // k * n + p
-    if (i >= 3 * n) return;
-    const int64_t p = i % n;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i = t / GS;   // k * n + p
+    const int sub = (int)(t % GS);
+    const bool live = i < 3 * n;
+    const int64_t ii = live ? i : 0;
+    const int64_t p = ii % n;
     const int C = body_chunks ? (int)body_chunks[p] : chunks;
     const int64_t stride = 3 * n;
     double a = 0.0;
-    for (int c0 = 0; c0 < C; c0 += kLoadBatch) {
-        double t[kLoadBatch];
+    if (live) {
+        for (int c0 = sub; c0 < C; c0 += GS * kLoadBatch) {
+            double v[kLoadBatch];
 #pragma unroll
-        for (int u = 0; u < kLoadBatch; ++u)
-            t[u] = (c0 + u < C) ? part[(int64_t)(c0 + u) * stride + i] : 0.0;
+            for (int u = 0; u < kLoadBatch; ++u) {
+                const int c = c0 + u * GS;
+                v[u] = (c < C) ? part[(int64_t)c * stride + ii] : 0.0;
+            }
 #pragma unroll
-        for (int u = 0; u < kLoadBatch; ++u)
-            if (c0 + u < C) a += t[u];
+            for (int u = 0; u < kLoadBatch; ++u)
+                if (c0 + u * GS < C) a += v[u];
+        }
     }
+    if (GS > 1) {
+        double total = a;
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int g = 1; g < GS; ++g) {
+            const double o = __shfl(a, lane + g, 64);
+            if (sub == 0) total += o;
+        }
+        a = total;
+    }
+    if (!live || sub != 0) return;
     bool finite = __builtin_isfinite(a);
     if (mode & kStoreAcc) acc[i] = a;
     if (mode & (kClose | kOpen)) {
@@ -280,8 +300,17 @@ hipError_t launch_step(const double* part, int chunks, const int8_t* body_chunks
                        double* vel, const double* pos_in, double* pos_out, double* acc,
                        double dt, int mode, uint32_t* flags, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_step, dim3(blocks_for(3 * n, kBlock)), dim3(kBlock), 0, s, part, chunks,
-                       body_chunks, n, vel, pos_in, pos_out, acc, 0.5 * dt, dt, mode, flags);
+    // several threads per element when there are many chunk partials to add
+    // (the ensemble's per-body chunk counts are at most 16)
+    const int max_chunks = body_chunks ? 16 : chunks;
+    if (max_chunks >= 16)
+        hipLaunchKernelGGL(k_step<4>, dim3(blocks_for(12 * n, kBlock)), dim3(kBlock), 0, s, part,
+                           chunks, body_chunks, n, vel, pos_in, pos_out, acc, 0.5 * dt, dt, mode,
+                           flags);
+    else
+        hipLaunchKernelGGL(k_step<1>, dim3(blocks_for(3 * n, kBlock)), dim3(kBlock), 0, s, part,
+                           chunks, body_chunks, n, vel, pos_in, pos_out, acc, 0.5 * dt, dt, mode,
+                           flags);
     return hipGetLastError();
 }
 

@@ -224,6 +224,27 @@ def autotune(pos, mass, G, precision="fp64", kind=0, small_mass=None):
     return t.as_dict(), float(ms.value)
 
 
+def autotune_batched(pos, mass, offsets, G, precision="fp64", small_mass=None):
+    """Autotunes the ensemble's force pass; returns (tile dict, ms per pass)."""
+    n = _mass(mass)
+    _state(pos, "pos", n)
+    dev = _same_device(pos, mass)
+    offs = [int(x) for x in offsets]
+    ns = len(offs) - 1
+    if ns < 1 or offs[-1] != n:
+        raise ValueError("offsets must have num_systems+1 entries ending at n")
+    p = _prec(precision)
+    arr = (ctypes.c_int64 * len(offs))(*offs)
+    ws = C.workspace(C.workspace_bytes(C.OP_BATCHED, n, num_systems=ns, steps=1, precision=p), dev)
+    t = C.Tile()
+    ms = ctypes.c_double(0)
+    st = C.load().nbody_autotune_batched(p, pos.data_ptr(), mass.data_ptr(), arr, ns, float(G),
+                                         _small(p, small_mass), ws.data_ptr(), ws.numel(),
+                                         C.stream_handle(dev), ctypes.byref(t), ctypes.byref(ms))
+    C.check(st, "nbody_autotune_batched")
+    return t.as_dict(), float(ms.value)
+
+
 def time_force(pos, mass, G, precision="fp64", kind=0, reps=50, small_mass=None):
     """Average ms of one force pass (HIP events on the current stream)."""
     n = _mass(mass)

@@ -286,6 +286,20 @@ def test_batched_matches_oracle(precision, variant):
         assert e <= tol, (k, x.n, e)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_batched_autotune_then_parity(precision):
+    systems, offs, pos, vel, mass = _small_ensemble(count=5)
+    tile, ms = nb.autotune_batched(T(pos), T(mass), offs, S.G_AU_DAY_MSUN, precision)
+    log(f"ensemble autotune {precision}: {tile} {ms:.4f} ms")
+    assert tile == nb.get_tile(2, precision, 0)
+    p, v = T(pos), T(vel)
+    nb.verlet_run_batched(p, v, T(mass), offs, S.G_AU_DAY_MSUN, 0.1, 20, precision=precision)
+    P = H(p)
+    for k, x in enumerate(systems):
+        pr, _ = oracle.verlet(x.pos, x.vel, x.mass, x.G, 0.1, 20)
+        assert rel(P[:, offs[k]:offs[k + 1]], pr) <= (1e-12 if precision == "fp64" else 1e-10)
+
+
 def test_batched_graph_replay_deterministic():
     systems, offs, pos, vel, mass = _small_ensemble(count=4)
     outs = []
