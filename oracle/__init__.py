@@ -77,6 +77,31 @@ def _load():
     return lib
 
 
+class use_library:
+    """Context manager that routes this module's calls to another build of
+    the oracle (the mutation tests load deliberately broken copies)."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _lib
+        _lib = None
+        real = _LIB
+        globals()["_LIB"] = self.path
+        try:
+            _load()
+        finally:
+            globals()["_LIB"] = real
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
 def _c(a, shape=None):
     a = np.ascontiguousarray(a, dtype=np.float64)
     if shape is not None and a.shape != shape:
