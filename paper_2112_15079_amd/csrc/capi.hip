@@ -74,13 +74,22 @@ int chunk_cap(int64_t n)
     return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxChunks, c));
 }
 
-// Defaults from tile sweeps on MI355X (the autotuner refines them): about
-// 8192 wavefronts in flight; scalar-operand sources for FP64 below ~3e4
-// bodies, LDS tiles with 4 targets per lane above; the split form prefers the
-// LDS tiles at every size.
+// Systems up to this size default to the single-workgroup variant.
+constexpr int64_t kSmallDefault = 256;
+
+// Defaults from tile sweeps on MI355X (the autotuner refines them): one
+// workgroup running whole steps for small systems; otherwise about 8192
+// wavefronts in flight; scalar-operand sources for FP64 below ~3e4 bodies,
+// LDS tiles with 4 targets per lane above; the split form prefers the LDS
+// tiles at every size.
 Tile heuristic_tile(int kind, int prec, int64_t n)
 {
     if (kind == 2) return Tile{2, 1, kBatchChunkMax, 0};   // ensemble: per-system chunks
+    if (kind == 0 && n <= kSmallDefault) {
+        const int64_t root = (int64_t)std::ceil(std::sqrt((double)n));
+        const int64_t S = std::max<int64_t>(1, std::min<int64_t>(root, 1024 / n));
+        return Tile{1, 16, (int)S, 3};
+    }
     Tile t{1, 1, 1, 0};
     if (kind == 0 && prec == NBODY_FP64) {
         if (n < 32768) t = Tile{1, n < 4096 ? 1 : 2, 1, 1};
@@ -101,7 +110,7 @@ Tile pick_tile(int kind, int prec, int64_t n)
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_tiles.find(std::make_tuple(kind, prec, size_class(n)));
-        if (it != g_tiles.end()) {
+        if (it != g_tiles.end() && !(it->second.variant == 3 && n > kSmallMax)) {
             Tile t = it->second;
             t.chunks = std::min(t.chunks, chunk_cap(n));
             return t;
@@ -364,7 +373,7 @@ int run_steps(const StepPlan& P, int64_t steps, hipStream_t stream, bool use_gra
     if (use_graph && middle >= 2 * kGraphSteps) {
         GraphKey key;
         key.v = {1, (uint64_t)P.prec, (uint64_t)P.tile.tpl, (uint64_t)P.tile.waves,
-                 (uint64_t)P.tile.chunks, (uint64_t)P.chunks, (uint64_t)P.n, bits(P.G), bits(P.dt),
+                 (uint64_t)P.tile.chunks, (uint64_t)P.tile.variant, (uint64_t)P.chunks, (uint64_t)P.n, bits(P.G), bits(P.dt),
                  ptrbits(P.mass), ptrbits(P.vel), ptrbits(P.buf[0]), ptrbits(P.buf[1]),
                  ptrbits(P.part), ptrbits(P.flags), ptrbits(P.nmaj), ptrbits(P.units),
                  (uint64_t)P.num_units, (uint64_t)P.grid, ptrbits(P.bchunks)};
@@ -433,7 +442,13 @@ int32_t nbody_accel(const double* pos, const double* vel, const double* mass, in
     double* part = at<double>(workspace, L.part);
     uint32_t* flags = at<uint32_t>(workspace, L.flags);
     double* gm = at<double>(workspace, L.gm);
+    const bool small = tile.variant == 3;
     if (precision == NBODY_FP64) {
+        if (small) {
+            NB_HIP(launch_run_small(0, tile, pos, nullptr, nullptr, mass, n, nullptr, G, 0.0, 0, 0,
+                                    0, acc_out, nullptr, flags, s));
+            return NBODY_OK;
+        }
         NB_HIP(launch_scale(mass, G, n, gm, s));
         NB_HIP(launch_force(0, tile, pos, mass, gm, n, nullptr, G, part, s));
         NB_HIP(launch_step(part, chunks, nullptr, n, nullptr, nullptr, nullptr, acc_out, 0.0,
@@ -447,10 +462,17 @@ int32_t nbody_accel(const double* pos, const double* vel, const double* mass, in
     double* acc_c = at<double>(workspace, L.alt_c);
     NB_HIP(launch_gather(perm, n, pos, pos_c, 3, s));
     NB_HIP(launch_gather(perm, n, mass, mass_c, 1, s));
-    NB_HIP(launch_scale(mass_c, G, n, gm, s));
-    NB_HIP(launch_force(1, tile, pos_c, mass_c, gm, n, at<int64_t>(workspace, L.nmaj), G, part, s));
-    NB_HIP(launch_step(part, chunks, nullptr, n, nullptr, nullptr, nullptr, acc_c, 0.0,
-                       kStoreAcc, flags, s));
+    if (small) {
+        NB_HIP(launch_run_small(1, tile, pos_c, nullptr, nullptr, mass_c, n,
+                                at<int64_t>(workspace, L.nmaj), G, 0.0, 0, 0, 0, acc_c, nullptr,
+                                flags, s));
+    } else {
+        NB_HIP(launch_scale(mass_c, G, n, gm, s));
+        NB_HIP(launch_force(1, tile, pos_c, mass_c, gm, n, at<int64_t>(workspace, L.nmaj), G, part,
+                            s));
+        NB_HIP(launch_step(part, chunks, nullptr, n, nullptr, nullptr, nullptr, acc_c, 0.0,
+                           kStoreAcc, flags, s));
+    }
     NB_HIP(launch_scatter(perm, n, acc_c, acc_out, 3, s));
     return NBODY_OK;
 }
@@ -482,7 +504,13 @@ int32_t nbody_verlet_run(double* pos, double* vel, const double* mass, int64_t n
     double* alt = at<double>(workspace, L.alt);
     double* gm = at<double>(workspace, L.gm);
     P.gm = gm;
+    const bool small = P.tile.variant == 3;
     if (precision == NBODY_FP64) {
+        if (small) {
+            NB_HIP(launch_run_small(0, P.tile, pos, pos, vel, mass, n, nullptr, G, dt, 0, steps,
+                                    steps, nullptr, nullptr, P.flags, s));
+            return NBODY_OK;
+        }
         P.mass = mass;
         P.vel = vel;
         NB_HIP(launch_scale(mass, G, n, gm, s));
@@ -506,12 +534,19 @@ int32_t nbody_verlet_run(double* pos, double* vel, const double* mass, int64_t n
     NB_HIP(launch_gather(perm, n, pos, pos_c, 3, s));
     NB_HIP(launch_gather(perm, n, vel, vel_c, 3, s));
     NB_HIP(launch_gather(perm, n, mass, mass_c, 1, s));
+    P.nmaj = at<int64_t>(workspace, L.nmaj);
+    if (small) {
+        NB_HIP(launch_run_small(1, P.tile, pos_c, pos_c, vel_c, mass_c, n, P.nmaj, G, dt, 0, steps,
+                                steps, nullptr, nullptr, P.flags, s));
+        NB_HIP(launch_scatter(perm, n, pos_c, pos, 3, s));
+        NB_HIP(launch_scatter(perm, n, vel_c, vel, 3, s));
+        return NBODY_OK;
+    }
     NB_HIP(launch_scale(mass_c, G, n, gm, s));
     P.mass = mass_c;
     P.vel = vel_c;
     P.buf[0] = pos_c;
     P.buf[1] = alt_c;
-    P.nmaj = at<int64_t>(workspace, L.nmaj);
     NB_TRY(run_steps(P, steps, s, true));
     NB_HIP(launch_scatter(perm, n, P.buf[steps & 1], pos, 3, s));
     NB_HIP(launch_scatter(perm, n, vel_c, vel, 3, s));
@@ -580,7 +615,8 @@ int32_t nbody_set_tile(int32_t kind, int32_t precision, int64_t n, const nbody_t
         return fail(NBODY_EINVAL, "bad arguments");
     if (kind == 2) n = 0;
     Tile t{tile_host->targets_per_lane, tile_host->waves, tile_host->chunks, tile_host->variant};
-    if (!tile_supported(t) || (kind == 1 && (t.tpl > 2 || t.waves > 4 || t.variant != 0)))
+    if (!tile_supported(t) || (kind == 1 && (t.tpl > 2 || t.waves > 4 || t.variant != 0)) ||
+        (t.variant == 3 && (kind != 0 || n > kSmallMax)))
         return fail(NBODY_EINVAL, "unsupported tile (%d, %d, %d)", t.tpl, t.waves, t.chunks);
     std::lock_guard<std::mutex> lk(g_mu);
     g_tiles[std::make_tuple(kind, precision, size_class(n))] = t;
@@ -644,9 +680,15 @@ int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const doubl
     NB_HIP(launch_scale(mass, G, n, at<double>(workspace, L.gm), s));
     NB_HIP(hipMemcpyAsync(ck_r(0), pos0, b3, hipMemcpyDeviceToDevice, s));
     NB_HIP(hipMemcpyAsync(ck_v(0), vel0, b3, hipMemcpyDeviceToDevice, s));
+    const bool small = P.tile.variant == 3;
     for (int64_t c = 0; c < nck; ++c) {
         const int64_t kseg = std::min(K, steps - c * K);
         NB_HIP(hipMemcpyAsync(ck_r(c + 1), ck_r(c), 2 * b3, hipMemcpyDeviceToDevice, s));
+        if (small) {
+            NB_HIP(launch_run_small(0, P.tile, ck_r(c + 1), ck_r(c + 1), ck_v(c + 1), mass, n,
+                                    nullptr, G, dt, 0, kseg, kseg, nullptr, nullptr, flags, s));
+            continue;
+        }
         P.vel = ck_v(c + 1);
         if (kseg & 1) {
             NB_HIP(hipMemcpyAsync(alt, ck_r(c + 1), b3, hipMemcpyDeviceToDevice, s));
@@ -683,7 +725,10 @@ int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const doubl
         const int64_t kseg = std::min(K, steps - c * K);
         NB_HIP(hipMemcpyAsync(seg, ck_r(c), b3, hipMemcpyDeviceToDevice, s));
         NB_HIP(hipMemcpyAsync(vtmp, ck_v(c), b3, hipMemcpyDeviceToDevice, s));
-        for (int64_t k = 0; k + 1 < kseg; ++k) {
+        if (small && kseg >= 2)
+            NB_HIP(launch_run_small(0, R.tile, seg, nullptr, vtmp, mass, n, nullptr, G, dt, 0,
+                                    kseg - 2, kseg, nullptr, seg + 3 * n, flags, s));
+        for (int64_t k = 0; !small && k + 1 < kseg; ++k) {
             double* pin = seg + k * 3 * n;
             NB_TRY(force(R, pin, s));
             const int mode = (k > 0 ? kClose : 0) | kOpen;
@@ -1040,7 +1085,11 @@ int32_t nbody_time_force(int32_t kind, int32_t precision, const double* pos, con
                          s, &b));
     const Tile t = pick_tile(kind, precision, n);
     auto once = [&]() -> int {
-        if (kind == 0) NB_HIP(launch_force(precision, t, b.pos, b.mass, b.gm, n, b.nmaj, G, b.part, s));
+        if (kind == 0 && t.variant == 3)
+            NB_HIP(launch_run_small(precision, t, b.pos, nullptr, nullptr, b.mass, n, b.nmaj, G, 0.0,
+                                    0, 0, 0, b.scratch, nullptr, nullptr, s));
+        else if (kind == 0)
+            NB_HIP(launch_force(precision, t, b.pos, b.mass, b.gm, n, b.nmaj, G, b.part, s));
         else           NB_HIP(launch_vjp(t, b.pos, b.mass, b.scratch, n, G, b.part, s));
         return NBODY_OK;
     };
@@ -1104,11 +1153,22 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
             }
         }
 
+    if (kind == 0 && n <= kSmallMax) {
+        // single workgroup: force pass, reduction and store in one launch
+        for (int S = 1; S <= kMaxChunks; S *= 2) {
+            const Tile t{1, 16, S, 3};
+            if (small_slices(n, t) == S) cands.push_back(t);
+        }
+    }
+
     hipEvent_t e0 = nullptr, e1 = nullptr;
     NB_HIP(hipEventCreate(&e0));
     NB_HIP(hipEventCreate(&e1));
     auto once = [&](const Tile& t) -> int {
-        if (kind == 0) {
+        if (kind == 0 && t.variant == 3) {
+            NB_HIP(launch_run_small(precision, t, pos_w, nullptr, nullptr, mass_w, n, nmaj, G, 0.0,
+                                    0, 0, 0, scratch, nullptr, nullptr, s));
+        } else if (kind == 0) {
             NB_HIP(launch_force(precision, t, pos_w, mass_w, b.gm, n, nmaj, G, part, s));
             NB_HIP(launch_step(part, effective_chunks(n, t), nullptr, n, nullptr, nullptr, nullptr,
                                scratch, 0.0, kStoreAcc, nullptr, s));

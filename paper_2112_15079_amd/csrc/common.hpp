@@ -18,10 +18,14 @@ struct Tile {
     int waves;        // wavefronts per workgroup: 1, 2, 4, 8
     int chunks;       // source chunks, 1..64
     int variant = 0;  // 0: sources staged in LDS; 1: sources as scalar operands;
-                      // 2: as 1, with the waves of a group splitting the sources
+                      // 2: as 1, with the waves of a group splitting the sources;
+                      // 3: one workgroup runs whole steps (n <= kSmallMax, tpl = 1,
+                      //    waves = 16, chunks = source slices per target)
 };
 
 constexpr int kMaxChunks = 64;
+// Largest system the single-workgroup variant holds in LDS.
+constexpr int kSmallMax = 512;
 
 // Source tile width (bodies staged in LDS per pass) = lanes of a workgroup.
 inline int tile_width(const Tile& t) { return 64 * t.waves; }
@@ -68,6 +72,22 @@ hipError_t launch_force_batched(int precision, const Tile& tile, const double* p
                                 const double* mass, const double* gm, int64_t n_total, double G,
                                 const BatchUnit* units, int64_t num_units, const int64_t* nmaj,
                                 int grid, double* part, hipStream_t s);
+
+// ----- small systems: one workgroup, whole steps (variant 3) ----------------
+// Source slices per target actually used for n bodies (0 if n > kSmallMax).
+int small_slices(int64_t n, const Tile& t);
+// Launch indices i0..i1 of a run of `steps` steps (i = 0..steps; launch i is
+// the force pass at r_i, the closing half kick for i > 0 and, for i < steps,
+// the opening half kick and the drift), state read from pos_in / vel and
+// written back to pos_out / vel at the end (pos_in == pos_out allowed).
+// acc != NULL (only with steps = 0): store a(r) in acc.  traj != NULL: the
+// position after each drift of launch i goes to traj + (i - i0) * 3n.
+// Split form (precision 1): sources [0, *nmaj) are the FP64 class.
+hipError_t launch_run_small(int precision, const Tile& tile, const double* pos_in,
+                            double* pos_out, double* vel, const double* mass, int64_t n,
+                            const int64_t* nmaj, double G, double dt, int64_t i0, int64_t i1,
+                            int64_t steps, double* acc, double* traj, uint32_t* flags,
+                            hipStream_t s);
 
 // ----- step epilogue (Eqs. (3)-(4) as kick-drift-kick) -----------------------
 enum StepMode : int {

@@ -15,9 +15,12 @@
 //  * the self pair is masked only in the tiles that overlap the workgroup's
 //    own targets.
 #include "common.hpp"
+#include "pair_math.hpp"
 
 namespace nb {
 namespace {
+
+using namespace pm;
 
 struct __attribute__((aligned(32))) Src {
     double x, y, z, gm;
@@ -26,46 +29,6 @@ struct __attribute__((aligned(32))) Src {
 // Padding source for the ragged last tile: massless and far away, so its
 // term is an exact zero without a branch.
 constexpr double kPad = 1.0e18;
-
-// G m r^-3 to full FP64 accuracy.  The FP32 hardware reciprocal square root
-// y0 (relative error below 2^-22) is exact in FP64 and so is y0^2, hence
-// e = 1 - r2 y0^2 is formed with a single rounding; then
-//   r^-3 = y0^3 (1 - e)^(-3/2) = y0^3 (1 + 3/2 e + 15/8 e^2 + O(e^3)),
-// and the dropped e^3 term is below 1e-18 relative.
-// c.a = 15/8 and c.b = 3/2 live in vector registers (see vreg_const) so that
-// the polynomial is a single v_fma_f64.
-struct PolyConst {
-    double a, b;
-};
-
-__device__ __forceinline__ double gm_rinv3_f64(double r2, double gm, const PolyConst& c)
-{
-    const double y = (double)__builtin_amdgcn_rsqf((float)r2);
-    const double y2 = y * y;
-    const double e = __builtin_fma(-r2, y2, 1.0);
-    const double g = gm * (y2 * y);
-    const double q = e * __builtin_fma(e, c.a, c.b);
-    return __builtin_fma(g, q, g);
-}
-
-// A loop-invariant constant kept in a vector register: gfx9 VOP3 encodings
-// take no literal operand and at most one scalar register, so a polynomial
-// with two non-inline constants otherwise costs two extra moves per use.
-__device__ __forceinline__ double vreg_const(double c)
-{
-    asm volatile("" : "+v"(c));
-    return c;
-}
-
-// G m r^-3 with one Newton step on the FP32 reciprocal square root:
-// y1 = y0 (1 + e/2), e = 1 - r2 y0^2, relative error about 3/2 e^2 (<= 3e-13).
-__device__ __forceinline__ double gm_rinv3_newton1(double r2, double gm)
-{
-    const double y = (double)__builtin_amdgcn_rsqf((float)r2);
-    const double e = __builtin_fma(-r2, y * y, 1.0);
-    const double y1 = __builtin_fma(0.5 * y, e, y);
-    return gm * (y1 * y1 * y1);
-}
 
 template <int T>
 struct Targets {
@@ -149,13 +112,6 @@ struct Kahan {
     float sx[T], sy[T], sz[T], cx[T], cy[T], cz[T];
 };
 
-__device__ __forceinline__ void kahan_add(float& s, float& c, float x)
-{
-    const float y = x - c;
-    const float t = s + y;
-    c = (t - s) - y;
-    s = t;
-}
 
 __device__ __forceinline__ float small_gm(double slot)
 {
@@ -554,6 +510,7 @@ __global__ __launch_bounds__(64 * W) void k_force_batched(const double* __restri
 
 bool tile_supported(const Tile& t)
 {
+    if (t.variant == 3) return t.tpl == 1 && t.waves == 16 && t.chunks >= 1 && t.chunks <= kMaxChunks;
     const bool tpl_ok = t.tpl == 1 || t.tpl == 2 || t.tpl == 4;
     const bool w_ok = t.waves == 1 || t.waves == 2 || t.waves == 4 || t.waves == 8;
     return tpl_ok && w_ok && t.chunks >= 1 && t.chunks <= kMaxChunks &&
@@ -562,6 +519,10 @@ bool tile_supported(const Tile& t)
 
 int64_t chunk_length(int64_t n, const Tile& t)
 {
+    if (t.variant == 3) {
+        const int64_t S = small_slices(n, t) < 1 ? 1 : small_slices(n, t);
+        return (n + S - 1) / S;
+    }
     const int64_t tw = t.variant == 2 ? (int64_t)kSGroup * t.waves
                      : t.variant == 1 ? (int64_t)kSGroup : tile_width(t);
     const int64_t per = (n + t.chunks - 1) / t.chunks;
@@ -645,7 +606,7 @@ hipError_t launch_force(int precision, const Tile& tile, const double* pos, cons
                         const double* gm, int64_t n, const int64_t* nmaj, double G, double* part,
                         hipStream_t s)
 {
-    if (tile.variant != 0 && !gm) return hipErrorInvalidValue;
+    if ((tile.variant != 0 && !gm) || tile.variant == 3) return hipErrorInvalidValue;
     const int64_t L = chunk_length(n, tile);
     const int chunks = effective_chunks(n, tile);
 #define NB_CASE(TT, WW)                                                                  \
@@ -662,7 +623,7 @@ hipError_t launch_force_batched(int precision, const Tile& tile, const double* p
                                 const BatchUnit* units, int64_t num_units, const int64_t* nmaj,
                                 int grid, double* part, hipStream_t s)
 {
-    if (tile.variant != 0 && !gm) return hipErrorInvalidValue;
+    if ((tile.variant != 0 && !gm) || tile.variant == 3) return hipErrorInvalidValue;
 #define NB_CASE(TT, WW)                                                                   \
     if (tile.tpl == TT && tile.waves == WW)                                               \
         return launch_batched_tw<TT, WW>(precision, tile.variant, pos, mass, gm, n_total, G, \

@@ -147,6 +147,34 @@ def test_tile_table():
     lib.nbody_reset_caches()
 
 
+def test_tile_table_single_workgroup_variant():
+    """Variant 3 (one workgroup runs whole steps): the heuristic for small
+    systems, and the shapes and sizes it accepts."""
+    lib = _lib()
+    lib.nbody_reset_caches()
+    t = C.Tile()
+    for prec in (0, 1):
+        assert lib.nbody_get_tile(0, prec, 131, ctypes.byref(t)) == C.NBODY_OK
+        # ceil(sqrt(131)) = 12 slices requested, capped at 1024 // 131 = 7
+        assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == (1, 16, 7, 3)
+        assert lib.nbody_get_tile(0, prec, 257, ctypes.byref(t)) == C.NBODY_OK and t.variant != 3
+    assert lib.nbody_get_tile(0, 0, 16, ctypes.byref(t)) == C.NBODY_OK and t.chunks == 4
+    assert lib.nbody_get_tile(1, 0, 131, ctypes.byref(t)) == C.NBODY_OK and t.variant == 0
+    assert lib.nbody_get_tile(2, 0, 0, ctypes.byref(t)) == C.NBODY_OK and t.variant != 3
+    assert lib.nbody_set_tile(0, 0, 400, ctypes.byref(C.Tile(1, 16, 2, 3))) == C.NBODY_OK
+    assert lib.nbody_get_tile(0, 0, 400, ctypes.byref(t)) == C.NBODY_OK
+    assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == (1, 16, 2, 3)
+    assert lib.nbody_set_tile(0, 0, 512, ctypes.byref(C.Tile(1, 16, 1, 3))) == C.NBODY_OK
+    # 513 shares 512's size class: the stored variant-3 shape is not used above 512
+    assert lib.nbody_set_tile(0, 0, 513, ctypes.byref(C.Tile(1, 16, 1, 3))) == C.NBODY_EINVAL
+    assert lib.nbody_get_tile(0, 0, 513, ctypes.byref(t)) == C.NBODY_OK and t.variant != 3
+    for bad in [(1, 8, 4, 3), (2, 16, 4, 3), (1, 16, 0, 3), (1, 16, 65, 3), (1, 1, 1, 4)]:
+        assert lib.nbody_set_tile(0, 0, 131, ctypes.byref(C.Tile(*bad))) == C.NBODY_EINVAL, bad
+    assert lib.nbody_set_tile(1, 0, 131, ctypes.byref(C.Tile(1, 16, 4, 3))) == C.NBODY_EINVAL
+    assert lib.nbody_set_tile(2, 0, 0, ctypes.byref(C.Tile(1, 16, 4, 3))) == C.NBODY_EINVAL
+    lib.nbody_reset_caches()
+
+
 def test_python_wrapper_rejects_cpu_tensors():
     torch = pytest.importorskip("torch")
     _lib()

@@ -26,9 +26,15 @@ def nrel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("steps,K", [(300, 7), (64, 64), (1, 5), (50, 1)])
-def test_adjoint_matches_oracle(steps, K):
+# forward tile: None = default for n = 40 (one workgroup running whole
+# steps); (1, 1, 2, 1) = the multi-workgroup force pass and step epilogue
+@pytest.mark.parametrize("tile", [None, (1, 1, 2, 1)])
+@pytest.mark.parametrize("steps,K", [(300, 7), (64, 64), (1, 5), (50, 1), (9, 2)])
+def test_adjoint_matches_oracle(steps, K, tile):
+    nb.reset_caches()
     s = S.solar_system(41, 20, n_major=19)
+    if tile is not None:
+        nb.set_tile(0, "fp64", s.n, *tile)
     rng = np.random.default_rng(steps)
     lr, lv = rng.normal(size=(3, s.n)), rng.normal(size=(3, s.n)) * 10
     gr, gv, gm = oracle.adjoint(s.pos, s.vel, s.mass, s.G, 0.1, steps, lr, lv)
@@ -41,6 +47,11 @@ def test_adjoint_matches_oracle(steps, K):
     assert nrel(H(pT), pr) <= 1e-12
     # inputs untouched
     assert np.array_equal(H(r), s.pos) and np.array_equal(H(v), s.vel)
+    # the forward half of the adjoint is the plain run, bit for bit
+    p, vv = T(s.pos), T(s.vel)
+    nb.verlet_run(p, vv, m, s.G, 0.1, steps)
+    assert np.array_equal(H(p), H(pT)) and np.array_equal(H(vv), H(vT))
+    nb.reset_caches()
 
 
 def test_adjoint_zero_steps_is_identity():

@@ -50,6 +50,8 @@ def _fresh_tiles():
 TILES = [(1, 1, 1, 0), (2, 1, 3, 0), (4, 1, 2, 0), (1, 2, 5, 0), (2, 4, 2, 0), (4, 8, 1, 0),
          (1, 8, 64, 0), (4, 2, 9, 0), (1, 1, 1, 1), (2, 1, 3, 1), (4, 2, 5, 1), (1, 4, 7, 1),
          (2, 8, 2, 1), (1, 2, 64, 1), (1, 2, 1, 2), (2, 4, 3, 2), (4, 2, 5, 2), (1, 8, 9, 2)]
+# one workgroup running whole steps (n <= 512): source slices per target
+SMALL_TILES = [(1, 16, 1, 3), (1, 16, 3, 3), (1, 16, 7, 3), (1, 16, 64, 3)]
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 131, 257, 1000, 2049])
@@ -57,7 +59,7 @@ def test_accel_fp64_shapes(n):
     s = S.solar_system(50 + n, max(n - 31, 0), n_major=min(30, max(n - 1, 0)))
     pos, mass = s.pos[:, :n], s.mass[:n]
     ref = oracle.accel(pos, mass, s.G)
-    for tile in TILES:
+    for tile in TILES + (SMALL_TILES if n <= 512 else []):
         nb.set_tile(0, "fp64", n, *tile)
         got = H(nb.accel(T(pos), T(mass), s.G))
         e = rel(got, ref)
@@ -65,13 +67,16 @@ def test_accel_fp64_shapes(n):
         assert e <= 1e-13
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("n", [3, 200, 1031])
 def test_accel_split_shapes(n, variant):
     """Split form on ragged sizes with the class boundary inside a group/tile."""
+    if variant == 3 and n > 512:
+        pytest.skip("the single-workgroup variant holds at most 512 bodies")
     s = S.solar_system(70 + n, max(n - 31, 0), n_major=min(30, n - 1))
     ref = oracle.accel(s.pos, s.mass, s.G)
-    for tile in [(1, 1, 1), (2, 2, 3), (4, 1, 2)]:
+    shapes = [(1, 16, 1), (1, 16, 2), (1, 16, 5)] if variant == 3 else [(1, 1, 1), (2, 2, 3), (4, 1, 2)]
+    for tile in shapes:
         nb.set_tile(0, "split", n, *tile, variant)
         got = H(nb.accel(T(s.pos), T(s.mass), s.G, precision="split"))
         e = rel(got, ref)
@@ -111,13 +116,29 @@ def test_accel_fp64_131072_sampled():
 # ---------------------------------------------------------------------------
 # Eqs. (3)-(4)
 
-def test_verlet_workload0_one_year():
+_ORACLE_RUNS = {}
+
+
+def _oracle_workload0():
+    if "w0" not in _ORACLE_RUNS:
+        s = S.config(0)
+        _ORACLE_RUNS["w0"] = oracle.verlet(s.pos, s.vel, s.mass, s.G, s.dt, s.steps)
+    return _ORACLE_RUNS["w0"]
+
+
+# None: the default shape for n = 131 (one workgroup running whole steps);
+# the others force the multi-workgroup force pass + step epilogue.
+@pytest.mark.parametrize("tile", [None, (1, 1, 2, 1), (2, 1, 1, 0), (1, 16, 3, 3)])
+def test_verlet_workload0_one_year(tile):
     s = S.config(0)
-    pr, vr = oracle.verlet(s.pos, s.vel, s.mass, s.G, s.dt, s.steps)
+    pr, vr = _oracle_workload0()
+    if tile is not None:
+        nb.set_tile(0, "fp64", s.n, *tile)
+    log(f"workload 0 tile={nb.get_tile(0, 'fp64', s.n)}")
     p, v = T(s.pos), T(s.vel)
     nb.verlet_run(p, v, T(s.mass), s.G, s.dt, s.steps)
     ep, ev = rel(H(p), pr), rel(H(v), vr)
-    log(f"workload 0, {s.steps} steps: pos rel={ep:.2e} vel rel={ev:.2e}")
+    log(f"workload 0, {s.steps} steps, tile={tile}: pos rel={ep:.2e} vel rel={ev:.2e}")
     assert ep <= 1e-10
     assert ev <= 1e-9
 
@@ -141,6 +162,40 @@ def test_verlet_step_counts(steps):
     nb.verlet_run(p, v, T(s.mass), s.G, 0.1, steps)
     assert rel(H(p), pr) <= 1e-12
     assert rel(H(v), vr) <= 1e-11
+
+
+def test_single_workgroup_run_across_launch_segments():
+    """Runs longer than one launch of the single-workgroup kernel (4096
+    launch indices) hand the state on through global memory: same results as
+    the oracle, and resuming at any step is bitwise identical."""
+    s = S.solar_system(11, 30, n_major=8)
+    steps = 4096 + 37
+    pr, vr = oracle.verlet(s.pos, s.vel, s.mass, s.G, 0.1, steps)
+    m = T(s.mass)
+    assert nb.get_tile(0, "fp64", s.n)["variant"] == 3
+    outs = []
+    for split in ([steps], [4095, 1, steps - 4096], [17, steps - 17]):
+        p, v = T(s.pos), T(s.vel)
+        for k in split:
+            nb.verlet_run(p, v, m, s.G, 0.1, k)
+        outs.append((H(p), H(v)))
+    assert rel(outs[0][0], pr) <= 1e-10 and rel(outs[0][1], vr) <= 1e-9
+    for p, v in outs[1:]:
+        assert np.array_equal(p, outs[0][0]) and np.array_equal(v, outs[0][1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_single_workgroup_matches_multi_workgroup(precision):
+    """The two paths for one small system agree to the parity tolerance."""
+    s = S.config(0)
+    m = T(s.mass)
+    res = []
+    for tile in [(1, 16, 7, 3), (1, 1, 2, 1)]:
+        nb.set_tile(0, precision, s.n, *tile)
+        p, v = T(s.pos), T(s.vel)
+        nb.verlet_run(p, v, m, s.G, s.dt, 500, precision=precision)
+        res.append(H(p))
+    assert rel(res[0], res[1]) <= 1e-11
 
 
 def test_verlet_zero_steps_is_noop():
@@ -315,6 +370,22 @@ def test_batched_graph_replay_deterministic():
 
 # ---------------------------------------------------------------------------
 # autotuner
+
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_autotune_small_system_then_parity(precision):
+    """At n = 131 the candidates include the single-workgroup variant."""
+    s = S.config(0)
+    tile, ms = nb.autotune(T(s.pos), T(s.mass), s.G, precision=precision)
+    log(f"autotune n=131 {precision}: {tile} {ms:.4f} ms/pass")
+    assert tile == nb.get_tile(0, precision, s.n)
+    ref = oracle.accel(s.pos, s.mass, s.G)
+    got = H(nb.accel(T(s.pos), T(s.mass), s.G, precision=precision))
+    assert rel(got, ref) <= (1e-13 if precision == "fp64" else 2e-12)
+    pr, _ = _oracle_workload0()
+    p, v = T(s.pos), T(s.vel)
+    nb.verlet_run(p, v, T(s.mass), s.G, s.dt, s.steps, precision=precision)
+    assert rel(H(p), pr) <= (1e-10 if precision == "fp64" else 1e-8)
+
 
 def test_autotune_then_parity():
     s = S.config(1)
