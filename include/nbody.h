@@ -152,7 +152,7 @@ int32_t nbody_get_flags(void* workspace, void* stream, int32_t clear, int32_t* f
  * one workgroup holds the system in LDS and runs whole steps, force pass,
  * reduction and kick-drift-kick, in one launch; chunks is then the number
  * of source slices per target (capped at 1024 / n).  The heuristic picks it
- * for n <= 256. */
+ * for n <= 192. */
 typedef struct {
     int32_t targets_per_lane;
     int32_t waves;

@@ -74,22 +74,22 @@ int chunk_cap(int64_t n)
     return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxChunks, c));
 }
 
-// Systems up to this size default to the single-workgroup variant.
-constexpr int64_t kSmallDefault = 256;
+// Systems up to this size default to the single-workgroup variant; up to
+// kShareDefault, to one workgroup of 8 waves per 64 targets (variant 2).
+constexpr int64_t kSmallDefault = 192;
+constexpr int64_t kShareDefault = 288;
 
 // Defaults from tile sweeps on MI355X (the autotuner refines them): one
-// workgroup running whole steps for small systems; otherwise about 8192
-// wavefronts in flight; scalar-operand sources for FP64 below ~3e4 bodies,
-// LDS tiles with 4 targets per lane above; the split form prefers the LDS
-// tiles at every size.
+// workgroup running whole steps for small systems (as many source slices as
+// 1024 lanes allow, at most 16); otherwise about 8192 wavefronts in flight;
+// scalar-operand sources for FP64 below ~3e4 bodies, LDS tiles with 4
+// targets per lane above; the split form prefers the LDS tiles at every size.
 Tile heuristic_tile(int kind, int prec, int64_t n)
 {
     if (kind == 2) return Tile{2, 1, kBatchChunkMax, 0};   // ensemble: per-system chunks
-    if (kind == 0 && n <= kSmallDefault) {
-        const int64_t root = (int64_t)std::ceil(std::sqrt((double)n));
-        const int64_t S = std::max<int64_t>(1, std::min<int64_t>(root, 1024 / n));
-        return Tile{1, 16, (int)S, 3};
-    }
+    if (kind == 0 && n <= kSmallDefault)
+        return Tile{1, 16, (int)std::max<int64_t>(1, std::min<int64_t>(16, 1024 / n)), 3};
+    if (kind == 0 && n <= kShareDefault) return Tile{1, 8, 1, 2};
     Tile t{1, 1, 1, 0};
     if (kind == 0 && prec == NBODY_FP64) {
         if (n < 32768) t = Tile{1, n < 4096 ? 1 : 2, 1, 1};
@@ -1155,7 +1155,7 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
 
     if (kind == 0 && n <= kSmallMax) {
         // single workgroup: force pass, reduction and store in one launch
-        for (int S = 1; S <= kMaxChunks; S *= 2) {
+        for (int S : {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 16, 24, 32, 48, 64}) {
             const Tile t{1, 16, S, 3};
             if (small_slices(n, t) == S) cands.push_back(t);
         }
@@ -1164,10 +1164,17 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
     hipEvent_t e0 = nullptr, e1 = nullptr;
     NB_HIP(hipEventCreate(&e0));
     NB_HIP(hipEventCreate(&e1));
+    // The single-workgroup variant is timed as it runs: kSmallPasses launch
+    // indices (force pass, reduction, kicks and drift, with dt = 0 so the
+    // state stays put) in one launch, on a copy of the state in `part`.
+    constexpr int kSmallPasses = 16;
+    double* r_small = part;
+    double* v_small = part + 3 * n;
     auto once = [&](const Tile& t) -> int {
         if (kind == 0 && t.variant == 3) {
-            NB_HIP(launch_run_small(precision, t, pos_w, nullptr, nullptr, mass_w, n, nmaj, G, 0.0,
-                                    0, 0, 0, scratch, nullptr, nullptr, s));
+            NB_HIP(launch_run_small(precision, t, r_small, r_small, v_small, mass_w, n, nmaj, G,
+                                    0.0, 0, kSmallPasses - 1, kSmallPasses, nullptr, nullptr,
+                                    nullptr, s));
         } else if (kind == 0) {
             NB_HIP(launch_force(precision, t, pos_w, mass_w, b.gm, n, nmaj, G, part, s));
             NB_HIP(launch_step(part, effective_chunks(n, t), nullptr, n, nullptr, nullptr, nullptr,
@@ -1184,6 +1191,13 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
     float best_ms = 1e30f;
     int status = NBODY_OK;
     for (const Tile& t : cands) {
+        if (t.variant == 3 &&
+            (hipMemcpyAsync(r_small, pos_w, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+                 hipSuccess ||
+             launch_fill(v_small, 0.0, 3 * n, s) != hipSuccess)) {
+            status = fail(NBODY_EHIP, "copying the state for the single-workgroup variant failed");
+            break;
+        }
         if ((status = once(t)) != NBODY_OK) break;
         if (hipEventRecord(e0, s) != hipSuccess) { status = fail(NBODY_EHIP, "event record"); break; }
         for (int r = 0; r < reps && status == NBODY_OK; ++r) status = once(t);
@@ -1195,6 +1209,7 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
         ms /= reps;
+        if (t.variant == 3) ms /= kSmallPasses;
         if (ms < best_ms) {
             best_ms = ms;
             best = t;

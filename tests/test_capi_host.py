@@ -155,10 +155,10 @@ def test_tile_table_single_workgroup_variant():
     t = C.Tile()
     for prec in (0, 1):
         assert lib.nbody_get_tile(0, prec, 131, ctypes.byref(t)) == C.NBODY_OK
-        # ceil(sqrt(131)) = 12 slices requested, capped at 1024 // 131 = 7
+        # as many slices as 1024 lanes allow: 1024 // 131 = 7
         assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == (1, 16, 7, 3)
-        assert lib.nbody_get_tile(0, prec, 257, ctypes.byref(t)) == C.NBODY_OK and t.variant != 3
-    assert lib.nbody_get_tile(0, 0, 16, ctypes.byref(t)) == C.NBODY_OK and t.chunks == 4
+        assert lib.nbody_get_tile(0, prec, 193, ctypes.byref(t)) == C.NBODY_OK and t.variant != 3
+    assert lib.nbody_get_tile(0, 0, 16, ctypes.byref(t)) == C.NBODY_OK and t.chunks == 16
     assert lib.nbody_get_tile(1, 0, 131, ctypes.byref(t)) == C.NBODY_OK and t.variant == 0
     assert lib.nbody_get_tile(2, 0, 0, ctypes.byref(t)) == C.NBODY_OK and t.variant != 3
     assert lib.nbody_set_tile(0, 0, 400, ctypes.byref(C.Tile(1, 16, 2, 3))) == C.NBODY_OK
