@@ -43,19 +43,27 @@ def parse():
     ap.add_argument("--workload", default="solar-10425",
                     choices=["solar-10425", "solar-131", "solar-131072", "ensemble", "adjoint",
                              "copy"])
-    ap.add_argument("--no-tune", action="store_true", help="use the heuristic tile shapes")
+    ap.add_argument("--tune", action="store_true",
+                    help="single-system workloads: autotune the force tiles first (the default "
+                         "is the library's sweep-derived heuristic; the ensemble always autotunes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU time budget of the oracle sample")
     ap.add_argument("--fd-coords", type=int, default=64, help="adjoint workload: FD coordinates")
-    ap.add_argument("--tile", default=None, help="fix the FP64 force tile as T,W,C (skips autotune)")
-    ap.add_argument("--split-tile", default=None, help="fix the split force tile as T,W,C")
+    ap.add_argument("--tile", default=None,
+                    help="fix the FP64 force tile as T,W,C[,variant] (skips autotune)")
+    ap.add_argument("--split-tile", default=None, help="fix the split force tile as T,W,C[,variant]")
     return ap.parse_args()
 
 
-def read_traffic(kernel_key):
-    """HBM traffic per launch from a committed rocprofv3 --pmc summary, if one
-    exists for this kernel (lines 'key: value' in profiles/<kernel_key>.txt)."""
+def tile_str(t):
+    return f"{t['targets_per_lane']},{t['waves']},{t['chunks']},{t['variant']}"
+
+
+def read_traffic(kernel_key, tile):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary
+    (profiles/<kernel_key>_traffic.txt, lines 'key: value'), if it was taken
+    with this tile shape; None otherwise."""
     path = os.path.join(ROOT, "profiles", f"{kernel_key}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -64,6 +72,8 @@ def read_traffic(kernel_key):
         if ":" in line and not line.lstrip().startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
+    if vals.get("tile") != tile_str(tile):
+        return None
     try:
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -116,7 +126,7 @@ def bench_single(args, k, S, nb, torch, np_, dev):
     for prec, fixed in (("fp64", args.tile), ("split", args.split_tile)):
         if fixed:
             nb.set_tile(0, prec, n, *[int(x) for x in fixed.split(",")])
-        elif not args.no_tune:
+        elif args.tune:
             tile, ms = nb.autotune(pos0, m, G, prec)
             log(f"autotune {prec}: {tile} {ms:.4f} ms per force pass")
         tiles[prec] = nb.get_tile(0, prec, n)
@@ -175,10 +185,14 @@ def bench_single(args, k, S, nb, torch, np_, dev):
     mssp = nb.time_force(pos0, m, G, "split", reps=reps)
     flops = FLOPS_PER_PAIR * pairs
     achieved = flops / (ms64 * 1e-3) / 1e12
-    roof = {"bound": "alu", "kernel": "k_force<fp64>", "achieved": round(achieved, 3),
+    t64 = tiles["fp64"]
+    kname = ({0: "k_force (LDS tiles)", 1: "k_force_s (scalar operands)",
+              2: "k_force_s (shared targets)", 3: "k_run_small (one workgroup)"}[t64["variant"]]
+             + f" FP64, tile {tile_str(t64)}")
+    roof = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3),
             "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-            "traffic": read_traffic(f"force_fp64_n{n}"),
+            "traffic": read_traffic(f"force_fp64_n{n}", t64),
             "ms_per_launch": round(ms64, 5), "flops_per_launch": flops,
             "split_ms_per_launch": round(mssp, 5)}
     log(f"force pass: fp64 {ms64:.4f} ms ({achieved:.2f} TFLOP/s alg.), split {mssp:.4f} ms")
@@ -269,10 +283,9 @@ def bench_ensemble(args, S, nb, torch, np, dev):
            "config": {"workload": "512 systems: Sun, 30 majors, U{100..8192} asteroids, seeds 100..611",
                       "bodies": int(offs[-1]), "pairs_per_step": pairs}}
     for prec in ("fp64", "split"):
-        if not args.no_tune:
-            tile, ms = nb.autotune_batched(pos0, m, offs, G, prec)
-            log(f"autotune ensemble {prec}: {tile} {ms:.3f} ms per force pass")
-            out.setdefault("tiles", {})[prec] = tile
+        tile, ms = nb.autotune_batched(pos0, m, offs, G, prec)
+        log(f"autotune ensemble {prec}: {tile} {ms:.3f} ms per force pass")
+        out.setdefault("tiles", {})[prec] = tile
         p, v = pos0.clone(), vel0.clone()
         nb.verlet_run_batched(p, v, m, offs, G, dt, W, precision=prec)
         torch.cuda.synchronize()
