@@ -53,6 +53,7 @@ class System:
     steps: int = 0
     counts: dict = field(default_factory=dict)
     name: str = ""
+    parent: np.ndarray | None = None   # (n,) body each body was placed about (0: the Sun)
 
     @property
     def n(self) -> int:
@@ -198,13 +199,13 @@ def _moons(rng, count, G, maj_pos, maj_vel, maj_mass):
     return p + maj_pos[:, parent], v + maj_vel[:, parent], m, parent
 
 
-def _assemble(parts, G, dt, steps, name, counts):
+def _assemble(parts, G, dt, steps, name, counts, parent=None):
     pos = np.concatenate([p[0] for p in parts], axis=1)
     vel = np.concatenate([p[1] for p in parts], axis=1)
     mass = np.concatenate([p[2] for p in parts])
     return System(np.ascontiguousarray(pos), np.ascontiguousarray(vel),
                   np.ascontiguousarray(mass), G=G, dt=dt, steps=steps,
-                  counts=counts, name=name)
+                  counts=counts, name=name, parent=parent)
 
 
 def _sun():
@@ -220,16 +221,19 @@ def solar_system(seed: int, n_small: int, n_moons: int = 0, n_heavy: int = 0,
     maj = _major(rng, n_major, G)
     parts.append(maj)
     counts = {"sun": 1, "major": n_major}
+    n = 1 + n_major + n_moons + n_heavy + n_small
+    body_parent = np.zeros(n, dtype=np.int64)
     if n_moons:
         p, v, m, parent = _moons(rng, n_moons, G, maj[0], maj[1], maj[2])
         parts.append((p, v, m))
         counts["moons"] = n_moons
+        body_parent[1 + n_major:1 + n_major + n_moons] = 1 + parent
     if n_heavy:
         parts.append(_belt(rng, n_heavy, G, 1e18, 1e21, log_mass=True))
         counts["heavy"] = n_heavy
     parts.append(_belt(rng, n_small, G, 1e12, 3e17, log_mass=False))
     counts["small"] = n_small
-    return _assemble(parts, G, dt, steps, name, counts)
+    return _assemble(parts, G, dt, steps, name, counts, body_parent)
 
 
 # ----------------------------------------------------------------------------
