@@ -271,7 +271,8 @@ def cpu_baseline(s, budget_s, k):
     n = s.n
     t1, _, _ = oracle.timed_verlet(s.pos, s.vel, s.mass, s.G, s.dt, 1)   # 2 force passes
     per_pass = t1 / 2
-    steps = int(max(1, min(2000, budget_s / max(per_pass, 1e-9) - 1)))
+    # a prefix of the workload's own run (all of it when that fits the budget)
+    steps = int(max(1, min(s.steps or 2000, budget_s / max(per_pass, 1e-9) - 1)))
     log(f"cpu baseline: oracle on {oracle.get_threads()} threads, {steps} steps")
     t, _, _ = oracle.timed_verlet(s.pos, s.vel, s.mass, s.G, s.dt, steps)
     pairs = (steps + 1) * n * (n - 1)
