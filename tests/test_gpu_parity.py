@@ -198,6 +198,47 @@ def test_single_workgroup_matches_multi_workgroup(precision):
     assert rel(res[0], res[1]) <= 1e-11
 
 
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+@pytest.mark.parametrize("n,slices", [(342, 2), (500, 2), (512, 1)])
+def test_single_workgroup_two_elements_per_lane(n, slices, precision):
+    """Above 341 bodies each lane of the single-workgroup kernel carries two
+    of the 3n (body, component) velocities through the steps."""
+    s = S.solar_system(90 + n, n - 31, n_major=30)
+    nb.set_tile(0, precision, n, 1, 16, slices, 3)
+    steps = 40
+    pr, vr = oracle.verlet(s.pos, s.vel, s.mass, s.G, 0.1, steps)
+    p, v = T(s.pos), T(s.vel)
+    nb.verlet_run(p, v, T(s.mass), s.G, 0.1, steps, precision=precision)
+    tol = 1e-12 if precision == "fp64" else 1e-10
+    assert rel(H(p), pr) <= tol and rel(H(v), vr) <= 10 * tol
+    got = H(nb.accel(T(s.pos), T(s.mass), s.G, precision=precision))
+    assert rel(got, oracle.accel(s.pos, s.mass, s.G)) <= (1e-13 if precision == "fp64" else 2e-12)
+
+
+@pytest.mark.parametrize("tile", [(1, 16, 7, 3), (1, 1, 2, 1), (1, 1, 1, 0)])
+@pytest.mark.parametrize("threshold,tol_sun,tol", [(0.0, 2e-12, 2e-12), (0.5, 2e-6, 1e-9),
+                                                   (2.0, 2e-6, 2e-6)])
+def test_split_class_boundaries(threshold, tol_sun, tol, tile):
+    """Split form with every body in the FP64 class (threshold 0), only the
+    Sun in it (0.5 Msun: the Sun's own acceleration is then made of FP32
+    terms only, and the planets' pulls, ~1e-3 of the Sun's, on the other
+    bodies) and none (2 Msun: every term in FP32, so the error is FP32's), for
+    the single-workgroup and the multi-workgroup kernels."""
+    s = S.config(0)
+    ref = oracle.accel(s.pos, s.mass, s.G)
+    nb.set_tile(0, "split", s.n, *tile)
+    got = H(nb.accel(T(s.pos), T(s.mass), s.G, precision="split", small_mass=threshold))
+    e_sun, e = rel(got[:, :1], ref[:, :1]), rel(got[:, 1:], ref[:, 1:])
+    log(f"split threshold {threshold} tile {tile}: rel Sun {e_sun:.2e}, others {e:.2e}")
+    assert np.isfinite(got).all() and e_sun <= tol_sun and e <= tol
+    p, v = T(s.pos), T(s.vel)
+    nb.verlet_run(p, v, T(s.mass), s.G, s.dt, 100, precision="split", small_mass=threshold)
+    pr, _ = oracle.verlet(s.pos, s.vel, s.mass, s.G, s.dt, 100)
+    P = H(p)
+    sun_tol, run_tol = {0.0: (1e-10, 1e-10), 0.5: (1e-6, 1e-8), 2.0: (1e-5, 1e-5)}[threshold]
+    assert rel(P[:, :1], pr[:, :1]) <= sun_tol and rel(P[:, 1:], pr[:, 1:]) <= run_tol
+
+
 def test_verlet_zero_steps_is_noop():
     s = S.config(0)
     p, v = T(s.pos), T(s.vel)
