@@ -665,7 +665,12 @@ int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const doubl
     auto ck_v = [&](int64_t k) { return ck + k * 6 * n + 3 * n; };
 
     // Forward run, storing (r, v) every K steps.  Each segment is a complete
-    // run of nbody_verlet_run, so segments chain bit for bit.
+    // run of nbody_verlet_run, so segments chain bit for bit.  A segment runs
+    // on fixed work buffers (position ping-pong w0/w1, velocity wv) from a
+    // captured graph, so every full-length segment replays the same graph.
+    double* w0 = alt;
+    double* w1 = u;
+    double* wv = vtmp;
     StepPlan P;
     P.prec = NBODY_FP64;
     P.tile = pick_tile(0, NBODY_FP64, n);
@@ -673,51 +678,72 @@ int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const doubl
     P.n = n;
     P.G = G;
     P.dt = dt;
+    double* gm = at<double>(workspace, L.gm);
     P.mass = mass;
-    P.gm = at<double>(workspace, L.gm);
+    P.gm = gm;
     P.part = part;
     P.flags = flags;
-    NB_HIP(launch_scale(mass, G, n, at<double>(workspace, L.gm), s));
+    P.vel = wv;
+    P.buf[0] = w0;
+    P.buf[1] = w1;
+    const bool small = P.tile.variant == 3;
+    const Tile vt = pick_tile(1, NBODY_FP64, n);
+    const int vchunks = effective_chunks(n, vt);
+    auto key_of = [&](uint64_t kind, int64_t kseg, uint64_t first) {
+        GraphKey key;
+        key.v = {kind, (uint64_t)kseg, first, (uint64_t)n, bits(G), bits(dt),
+                 (uint64_t)P.tile.tpl, (uint64_t)P.tile.waves, (uint64_t)P.tile.chunks,
+                 (uint64_t)P.tile.variant, (uint64_t)vt.tpl, (uint64_t)vt.waves,
+                 (uint64_t)vt.chunks, ptrbits(mass), ptrbits(P.gm), ptrbits(part), ptrbits(flags),
+                 ptrbits(w0), ptrbits(w1), ptrbits(wv), ptrbits(seg), ptrbits(lam_r),
+                 ptrbits(lam_v), ptrbits(g_m)};
+        return key;
+    };
+    // segments longer than this run their launches directly instead of from
+    // a graph (a graph is captured once per segment length and replayed)
+    constexpr int64_t kMaxGraphSegment = 1024;
+    auto maybe_graph = [&](const GraphKey& key, int64_t kseg, auto&& body) -> int {
+        if (kseg <= kMaxGraphSegment) return run_graph(key, s, body);
+        return body(s);
+    };
+    NB_HIP(launch_scale(mass, G, n, gm, s));
     NB_HIP(hipMemcpyAsync(ck_r(0), pos0, b3, hipMemcpyDeviceToDevice, s));
     NB_HIP(hipMemcpyAsync(ck_v(0), vel0, b3, hipMemcpyDeviceToDevice, s));
-    const bool small = P.tile.variant == 3;
     for (int64_t c = 0; c < nck; ++c) {
         const int64_t kseg = std::min(K, steps - c * K);
-        NB_HIP(hipMemcpyAsync(ck_r(c + 1), ck_r(c), 2 * b3, hipMemcpyDeviceToDevice, s));
+        NB_HIP(hipMemcpyAsync(w0, ck_r(c), b3, hipMemcpyDeviceToDevice, s));
+        NB_HIP(hipMemcpyAsync(wv, ck_v(c), b3, hipMemcpyDeviceToDevice, s));
+        const double* r_end = w0;
         if (small) {
-            NB_HIP(launch_run_small(0, P.tile, ck_r(c + 1), ck_r(c + 1), ck_v(c + 1), mass, n,
-                                    nullptr, G, dt, 0, kseg, kseg, nullptr, nullptr, flags, s));
-            continue;
-        }
-        P.vel = ck_v(c + 1);
-        if (kseg & 1) {
-            NB_HIP(hipMemcpyAsync(alt, ck_r(c + 1), b3, hipMemcpyDeviceToDevice, s));
-            P.buf[0] = alt;
-            P.buf[1] = ck_r(c + 1);
+            NB_HIP(launch_run_small(0, P.tile, w0, w0, wv, mass, n, nullptr, G, dt, 0, kseg, kseg,
+                                    nullptr, nullptr, flags, s));
         } else {
-            P.buf[0] = ck_r(c + 1);
-            P.buf[1] = alt;
+            NB_TRY(maybe_graph(key_of(2, kseg, 0), kseg, [&](hipStream_t cs) {
+                for (int64_t i = 0; i <= kseg; ++i) {
+                    const int st = step_launch(P, i, kseg, cs);
+                    if (st != NBODY_OK) return st;
+                }
+                return (int)NBODY_OK;
+            }));
+            r_end = P.buf[kseg & 1];
         }
-        NB_TRY(run_steps(P, kseg, s, false));
+        NB_HIP(hipMemcpyAsync(ck_r(c + 1), r_end, b3, hipMemcpyDeviceToDevice, s));
+        NB_HIP(hipMemcpyAsync(ck_v(c + 1), wv, b3, hipMemcpyDeviceToDevice, s));
     }
     if (pos_out) NB_HIP(hipMemcpyAsync(pos_out, ck_r(nck), b3, hipMemcpyDeviceToDevice, s));
     if (vel_out) NB_HIP(hipMemcpyAsync(vel_out, ck_v(nck), b3, hipMemcpyDeviceToDevice, s));
 
-    // Reverse sweep (one transpose-Jacobian product of Eq. (1) per force pass).
-    const Tile vt = pick_tile(1, NBODY_FP64, n);
-    const int vchunks = effective_chunks(n, vt);
+    // Reverse sweep: one transpose-Jacobian product of Eq. (1) per force
+    // pass, its chunk reduction fused with the adjoint of the drift that
+    // precedes the pass (lam_v += dt lam_r), the cotangent c lam_v scaled
+    // inside the product.
     NB_HIP(hipMemcpyAsync(lam_r, grad_posT, b3, hipMemcpyDeviceToDevice, s));
     NB_HIP(hipMemcpyAsync(lam_v, grad_velT, b3, hipMemcpyDeviceToDevice, s));
     NB_HIP(launch_fill(g_m, 0.0, n, s));
-    auto vjp_into = [&](const double* r) -> int {
-        NB_HIP(launch_vjp(vt, r, mass, u, n, G, part, s));
-        NB_HIP(launch_vjp_reduce(part, vchunks, n, lam_r, g_m, s));
-        return NBODY_OK;
-    };
     if (steps > 0) {
         // closing half kick of the last step: v_T = v_{T-1/2} + dt/2 a(r_T)
-        NB_HIP(launch_scale(lam_v, 0.5 * dt, 3 * n, u, s));
-        NB_TRY(vjp_into(ck_r(nck)));
+        NB_HIP(launch_vjp(vt, ck_r(nck), mass, lam_v, 0.5 * dt, n, G, part, s));
+        NB_HIP(launch_vjp_reduce(part, vchunks, n, lam_r, g_m, lam_v, dt, true, s));
     }
     StepPlan R = P;   // recompute plan: positions of one segment into seg slots
     R.vel = vtmp;
@@ -725,24 +751,28 @@ int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const doubl
         const int64_t kseg = std::min(K, steps - c * K);
         NB_HIP(hipMemcpyAsync(seg, ck_r(c), b3, hipMemcpyDeviceToDevice, s));
         NB_HIP(hipMemcpyAsync(vtmp, ck_v(c), b3, hipMemcpyDeviceToDevice, s));
-        if (small && kseg >= 2)
-            NB_HIP(launch_run_small(0, R.tile, seg, nullptr, vtmp, mass, n, nullptr, G, dt, 0,
-                                    kseg - 2, kseg, nullptr, seg + 3 * n, flags, s));
-        for (int64_t k = 0; !small && k + 1 < kseg; ++k) {
-            double* pin = seg + k * 3 * n;
-            NB_TRY(force(R, pin, s));
-            const int mode = (k > 0 ? kClose : 0) | kOpen;
-            NB_HIP(launch_step(part, R.chunks, nullptr, n, vtmp, pin, pin + 3 * n, nullptr, dt,
-                               mode, flags, s));
-        }
-        for (int64_t k = kseg - 1; k >= 0; --k) {
-            const int64_t i = c * K + k;
-            // drift r_{i+1} = r_i + dt v_{i+1/2}
-            NB_HIP(launch_axpy(lam_r, dt, 3 * n, lam_v, s));
-            // kick v_{i+1/2} = v_{i-1/2} + dt a(r_i)   (dt/2 for i = 0)
-            NB_HIP(launch_scale(lam_v, i > 0 ? dt : 0.5 * dt, 3 * n, u, s));
-            NB_TRY(vjp_into(seg + k * 3 * n));
-        }
+        NB_TRY(maybe_graph(key_of(3, kseg, c == 0), kseg, [&](hipStream_t cs) -> int {
+            // positions r_{cK+1} .. r_{cK+kseg-1} of the segment into seg slots
+            if (small && kseg >= 2)
+                NB_HIP(launch_run_small(0, R.tile, seg, nullptr, vtmp, mass, n, nullptr, G, dt, 0,
+                                        kseg - 2, kseg, nullptr, seg + 3 * n, flags, cs));
+            for (int64_t k = 0; !small && k + 1 < kseg; ++k) {
+                double* pin = seg + k * 3 * n;
+                NB_TRY(force(R, pin, cs));
+                const int mode = (k > 0 ? kClose : 0) | kOpen;
+                NB_HIP(launch_step(part, R.chunks, nullptr, n, vtmp, pin, pin + 3 * n, nullptr, dt,
+                                   mode, flags, cs));
+            }
+            for (int64_t k = kseg - 1; k >= 0; --k) {
+                const int64_t i = c * K + k;
+                // kick v_{i+1/2} = v_{i-1/2} + dt a(r_i)   (dt/2 for i = 0); the
+                // drift r_i = r_{i-1} + dt v_{i-1/2} before it (i > 0)
+                NB_HIP(launch_vjp(vt, seg + k * 3 * n, mass, lam_v, i > 0 ? dt : 0.5 * dt, n, G,
+                                  part, cs));
+                NB_HIP(launch_vjp_reduce(part, vchunks, n, lam_r, g_m, lam_v, dt, i > 0, cs));
+            }
+            return (int)NBODY_OK;
+        }));
     }
     NB_HIP(hipMemcpyAsync(grad_pos0, lam_r, b3, hipMemcpyDeviceToDevice, s));
     NB_HIP(hipMemcpyAsync(grad_vel0, lam_v, b3, hipMemcpyDeviceToDevice, s));
@@ -1090,7 +1120,7 @@ int32_t nbody_time_force(int32_t kind, int32_t precision, const double* pos, con
                                     0, 0, 0, b.scratch, nullptr, nullptr, s));
         else if (kind == 0)
             NB_HIP(launch_force(precision, t, b.pos, b.mass, b.gm, n, b.nmaj, G, b.part, s));
-        else           NB_HIP(launch_vjp(t, b.pos, b.mass, b.scratch, n, G, b.part, s));
+        else           NB_HIP(launch_vjp(t, b.pos, b.mass, b.scratch, 1.0, n, G, b.part, s));
         return NBODY_OK;
     };
     NB_TRY(once());
@@ -1180,7 +1210,7 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
             NB_HIP(launch_step(part, effective_chunks(n, t), nullptr, n, nullptr, nullptr, nullptr,
                                scratch, 0.0, kStoreAcc, nullptr, s));
         } else {
-            NB_HIP(launch_vjp(t, pos_w, mass_w, scratch, n, G, part, s));
+            NB_HIP(launch_vjp(t, pos_w, mass_w, scratch, 1.0, n, G, part, s));
         }
         return NBODY_OK;
     };

@@ -123,12 +123,14 @@ hipError_t launch_momenta(const double* pos, const double* vel, const double* ma
                           double* out, hipStream_t s);
 
 // ----- adjoint (transpose of the Jacobian of Eq. (1)) ------------------------------
-// For cotangent u (on accelerations): lam_r[q] += (J^T u)_q, g_m[q] += (M^T u)_q.
-hipError_t launch_vjp(const Tile& tile, const double* pos, const double* mass, const double* u,
-                      int64_t n, double G, double* part, hipStream_t s);
-// lam_r += sum of chunk partials (planes 0..2), g_m += plane 3.
+// Chunk partials of (J^T u, M^T u) for the cotangent u = cu * lam on the
+// accelerations (variant-0 tiles, tpl <= 2, waves <= 4).
+hipError_t launch_vjp(const Tile& tile, const double* pos, const double* mass, const double* lam,
+                      double cu, int64_t n, double G, double* part, hipStream_t s);
+// lam_r += sum of chunk partials (planes 0..2), g_m += plane 3; then, if
+// drift, lam_v += dt * lam_r (the adjoint of the drift before this pass).
 hipError_t launch_vjp_reduce(const double* part, int chunks, int64_t n, double* lam_r,
-                             double* g_m, hipStream_t s);
+                             double* g_m, double* lam_v, double dt, bool drift, hipStream_t s);
 // u = c * lam_v
 hipError_t launch_scale(const double* x, double c, int64_t m, double* y, hipStream_t s);
 // y += c * x

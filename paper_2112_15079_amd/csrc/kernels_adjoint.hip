@@ -73,12 +73,12 @@ __device__ __forceinline__ void vjp_sweep(const ASrc* __restrict__ tile, int j0,
 }
 
 // part[c*4n + k*n + q]: chunk-c partials of G (K (m_q u_j - m_j u_q)) (k < 3)
-// and of -G u_j . d / |d|^3 (k = 3).
+// and of -G u_j . d / |d|^3 (k = 3), for the cotangent u = cu * lam.
 template <int T, int W>
 __global__ __launch_bounds__(64 * W) void k_vjp(const double* __restrict__ pos,
                                                 const double* __restrict__ mass,
-                                                const double* __restrict__ u, int64_t n,
-                                                int64_t chunk_len, double G,
+                                                const double* __restrict__ lam, double cu,
+                                                int64_t n, int64_t chunk_len, double G,
                                                 double* __restrict__ part)
 {
     constexpr int NT = 64 * W;
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(64 * W) void k_vjp(const double* __restrict__ pos,
         qid[t] = (int)p;
         qx[t] = pos[q]; qy[t] = pos[n + q]; qz[t] = pos[2 * n + q];
         qm[t] = mass[q];
-        ux[t] = u[q]; uy[t] = u[n + q]; uz[t] = u[2 * n + q];
+        ux[t] = cu * lam[q]; uy[t] = cu * lam[n + q]; uz[t] = cu * lam[2 * n + q];
         ox[t] = 0.0; oy[t] = 0.0; oz[t] = 0.0; og[t] = 0.0;
     }
     const int64_t tend = tb0 + (int64_t)NT * T;
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(64 * W) void k_vjp(const double* __restrict__ pos,
         if (j < jend) {
             s.x = pos[j]; s.y = pos[n + j]; s.z = pos[2 * n + j];
             s.m = mass[j];
-            s.ux = u[j]; s.uy = u[n + j]; s.uz = u[2 * n + j];
+            s.ux = cu * lam[j]; s.uy = cu * lam[n + j]; s.uz = cu * lam[2 * n + j];
         } else {
             s.x = kPad; s.y = kPad; s.z = kPad;
             s.m = 0.0; s.ux = 0.0; s.uy = 0.0; s.uz = 0.0;
@@ -137,18 +137,29 @@ __global__ __launch_bounds__(64 * W) void k_vjp(const double* __restrict__ pos,
 
 constexpr int kBlock = 256;
 
+// lam_r += sum of the chunk partials of planes 0..2, g_m += plane 3 (chunks
+// in ascending order); then, when `drift` is set, the adjoint of the drift
+// that precedes this force pass in the reverse sweep: lam_v += dt lam_r.
 __global__ __launch_bounds__(kBlock) void k_vjp_reduce(const double* __restrict__ part,
                                                        int chunks, int64_t n,
                                                        double* __restrict__ lam_r,
-                                                       double* __restrict__ g_m)
+                                                       double* __restrict__ g_m,
+                                                       double* __restrict__ lam_v, double dt,
+                                                       int drift)
 {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q >= n) return;
     for (int k = 0; k < 4; ++k) {
         double a = 0.0;
         for (int c = 0; c < chunks; ++c) a += part[(int64_t)c * 4 * n + (int64_t)k * n + q];
-        if (k < 3) lam_r[(int64_t)k * n + q] += a;
-        else       g_m[q] += a;
+        if (k < 3) {
+            const int64_t e = (int64_t)k * n + q;
+            const double r = lam_r[e] + a;
+            lam_r[e] = r;
+            if (drift) lam_v[e] = __builtin_fma(dt, r, lam_v[e]);
+        } else {
+            g_m[q] += a;
+        }
     }
 }
 
@@ -177,32 +188,34 @@ __global__ __launch_bounds__(kBlock) void k_fill(double* __restrict__ y, double 
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <int T, int W>
-static hipError_t vjp_tw(const double* pos, const double* mass, const double* u, int64_t n,
-                         int64_t L, int chunks, double G, double* part, hipStream_t s)
+static hipError_t vjp_tw(const double* pos, const double* mass, const double* lam, double cu,
+                         int64_t n, int64_t L, int chunks, double G, double* part, hipStream_t s)
 {
     constexpr int NT = 64 * W;
     const dim3 grid((unsigned)((n + (int64_t)NT * T - 1) / ((int64_t)NT * T)), (unsigned)chunks);
-    hipLaunchKernelGGL((k_vjp<T, W>), grid, dim3(NT), 0, s, pos, mass, u, n, L, G, part);
+    hipLaunchKernelGGL((k_vjp<T, W>), grid, dim3(NT), 0, s, pos, mass, lam, cu, n, L, G, part);
     return hipGetLastError();
 }
 
-hipError_t launch_vjp(const Tile& tile, const double* pos, const double* mass, const double* u,
-                      int64_t n, double G, double* part, hipStream_t s)
+hipError_t launch_vjp(const Tile& tile, const double* pos, const double* mass, const double* lam,
+                      double cu, int64_t n, double G, double* part, hipStream_t s)
 {
+    if (tile.variant != 0) return hipErrorInvalidValue;
     const int64_t L = chunk_length(n, tile);
     const int chunks = (int)((n + L - 1) / L);
-#define NB_CASE(TT, WW) \
-    if (tile.tpl == TT && tile.waves == WW) return vjp_tw<TT, WW>(pos, mass, u, n, L, chunks, G, part, s);
+#define NB_CASE(TT, WW)                                                                 \
+    if (tile.tpl == TT && tile.waves == WW)                                             \
+        return vjp_tw<TT, WW>(pos, mass, lam, cu, n, L, chunks, G, part, s);
     NB_CASE(1, 1) NB_CASE(1, 2) NB_CASE(1, 4) NB_CASE(2, 1) NB_CASE(2, 2) NB_CASE(2, 4)
 #undef NB_CASE
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_vjp_reduce(const double* part, int chunks, int64_t n, double* lam_r,
-                             double* g_m, hipStream_t s)
+                             double* g_m, double* lam_v, double dt, bool drift, hipStream_t s)
 {
     hipLaunchKernelGGL(k_vjp_reduce, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, part,
-                       chunks, n, lam_r, g_m);
+                       chunks, n, lam_r, g_m, lam_v, dt, drift ? 1 : 0);
     return hipGetLastError();
 }
 
