@@ -90,6 +90,15 @@ Tile heuristic_tile(int kind, int prec, int64_t n)
     if (kind == 0 && n <= kSmallDefault)
         return Tile{1, 16, (int)std::max<int64_t>(1, std::min<int64_t>(16, 1024 / n)), 3};
     if (kind == 0 && n <= kShareDefault) return Tile{1, 8, 1, 2};
+    if (kind == 1) {
+        // transpose-Jacobian pass: one wave per 64 targets, sources split in
+        // chunks of >= 16 until about 4096 waves are in flight
+        const int64_t tb = (n + 63) / 64;
+        const int64_t c = std::min<int64_t>({std::max<int64_t>(1, 4096 / tb),
+                                             std::max<int64_t>(1, n / 16),
+                                             (int64_t)chunk_cap(n)});
+        return Tile{1, 1, (int)c, 0};
+    }
     Tile t{1, 1, 1, 0};
     if (kind == 0 && prec == NBODY_FP64) {
         if (n < 32768) t = Tile{1, n < 4096 ? 1 : 2, 1, 1};
@@ -688,7 +697,7 @@ int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const doubl
     P.buf[1] = w1;
     const bool small = P.tile.variant == 3;
     const Tile vt = pick_tile(1, NBODY_FP64, n);
-    const int vchunks = effective_chunks(n, vt);
+    const int vchunks = vjp_chunks(n, vt);
     auto key_of = [&](uint64_t kind, int64_t kseg, uint64_t first) {
         GraphKey key;
         key.v = {kind, (uint64_t)kseg, first, (uint64_t)n, bits(G), bits(dt),

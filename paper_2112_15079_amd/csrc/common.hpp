@@ -123,8 +123,12 @@ hipError_t launch_momenta(const double* pos, const double* vel, const double* ma
                           double* out, hipStream_t s);
 
 // ----- adjoint (transpose of the Jacobian of Eq. (1)) ------------------------------
+// Source chunks of the transpose-Jacobian pass: multiples of 8 sources
+// (the last LDS tile of a chunk may be partly used), at most t.chunks.
+int64_t vjp_chunk_length(int64_t n, const Tile& t);
+int vjp_chunks(int64_t n, const Tile& t);
 // Chunk partials of (J^T u, M^T u) for the cotangent u = cu * lam on the
-// accelerations (variant-0 tiles, tpl <= 2, waves <= 4).
+// accelerations (variant-0 tiles, tpl <= 2, waves <= 4), vjp_chunks of them.
 hipError_t launch_vjp(const Tile& tile, const double* pos, const double* mass, const double* lam,
                       double cu, int64_t n, double G, double* part, hipStream_t s);
 // lam_r += sum of chunk partials (planes 0..2), g_m += plane 3; then, if

@@ -29,8 +29,9 @@ __device__ __forceinline__ double rinv_f64(double r2)
     return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
 }
 
+// Sources [0, cnt) of the LDS tile (cnt is the same for the whole workgroup).
 template <int T, int W, bool MASK>
-__device__ __forceinline__ void vjp_sweep(const ASrc* __restrict__ tile, int j0,
+__device__ __forceinline__ void vjp_sweep(const ASrc* __restrict__ tile, int cnt, int j0,
                                           const double (&qx)[T], const double (&qy)[T],
                                           const double (&qz)[T], const double (&qm)[T],
                                           const double (&ux)[T], const double (&uy)[T],
@@ -38,9 +39,8 @@ __device__ __forceinline__ void vjp_sweep(const ASrc* __restrict__ tile, int j0,
                                           double (&ox)[T], double (&oy)[T], double (&oz)[T],
                                           double (&og)[T])
 {
-    constexpr int NT = 64 * W;
 #pragma unroll 2
-    for (int jj = 0; jj < NT; ++jj) {
+    for (int jj = 0; jj < cnt; ++jj) {
         const ASrc s = tile[jj];
 #pragma unroll
         for (int t = 0; t < T; ++t) {
@@ -118,9 +118,12 @@ __global__ __launch_bounds__(64 * W) void k_vjp(const double* __restrict__ pos,
         __syncthreads();
         tile[tid] = s;
         __syncthreads();
+        // chunks are multiples of 8 sources, not of the tile width: the last
+        // tile of a chunk is swept only over its valid sources
+        const int cnt = (int)((jend - j0) < NT ? (jend - j0) : NT);
         const bool diag = (j0 < tend) && (tb0 < j0 + NT);
-        if (diag) vjp_sweep<T, W, true>(tile, (int)j0, qx, qy, qz, qm, ux, uy, uz, qid, ox, oy, oz, og);
-        else      vjp_sweep<T, W, false>(tile, (int)j0, qx, qy, qz, qm, ux, uy, uz, qid, ox, oy, oz, og);
+        if (diag) vjp_sweep<T, W, true>(tile, cnt, (int)j0, qx, qy, qz, qm, ux, uy, uz, qid, ox, oy, oz, og);
+        else      vjp_sweep<T, W, false>(tile, cnt, (int)j0, qx, qy, qz, qm, ux, uy, uz, qid, ox, oy, oz, og);
     }
     double* pc = part + c * 4 * n;
 #pragma unroll
@@ -137,9 +140,15 @@ __global__ __launch_bounds__(64 * W) void k_vjp(const double* __restrict__ pos,
 
 constexpr int kBlock = 256;
 
-// lam_r += sum of the chunk partials of planes 0..2, g_m += plane 3 (chunks
-// in ascending order); then, when `drift` is set, the adjoint of the drift
-// that precedes this force pass in the reverse sweep: lam_v += dt lam_r.
+// lam_r += sum of the chunk partials of planes 0..2, g_m += plane 3; then,
+// when `drift` is set, the adjoint of the drift that precedes this force pass
+// in the reverse sweep: lam_v += dt lam_r.  GS threads per (plane, body)
+// element: thread `sub` adds chunks sub, sub + GS, ... in ascending order with
+// its loads batched, and lane 0 of the group adds the GS sub-sums in order
+// (fixed order: deterministic).
+constexpr int kLoadBatch = 8;
+
+template <int GS>
 __global__ __launch_bounds__(kBlock) void k_vjp_reduce(const double* __restrict__ part,
                                                        int chunks, int64_t n,
                                                        double* __restrict__ lam_r,
@@ -147,19 +156,43 @@ __global__ __launch_bounds__(kBlock) void k_vjp_reduce(const double* __restrict_
                                                        double* __restrict__ lam_v, double dt,
                                                        int drift)
 {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q >= n) return;
-    for (int k = 0; k < 4; ++k) {
-        double a = 0.0;
-        for (int c = 0; c < chunks; ++c) a += part[(int64_t)c * 4 * n + (int64_t)k * n + q];
-        if (k < 3) {
-            const int64_t e = (int64_t)k * n + q;
-            const double r = lam_r[e] + a;
-            lam_r[e] = r;
-            if (drift) lam_v[e] = __builtin_fma(dt, r, lam_v[e]);
-        } else {
-            g_m[q] += a;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i = t / GS;   // k * n + q, k = 0..3
+    const int sub = (int)(t % GS);
+    const bool live = i < 4 * n;
+    const int64_t ii = live ? i : 0;
+    const int64_t stride = 4 * n;
+    double a = 0.0;
+    if (live) {
+        for (int c0 = sub; c0 < chunks; c0 += GS * kLoadBatch) {
+            double v[kLoadBatch];
+#pragma unroll
+            for (int u = 0; u < kLoadBatch; ++u) {
+                const int c = c0 + u * GS;
+                v[u] = (c < chunks) ? part[(int64_t)c * stride + ii] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kLoadBatch; ++u)
+                if (c0 + u * GS < chunks) a += v[u];
         }
+    }
+    if (GS > 1) {
+        double total = a;
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int g = 1; g < GS; ++g) {
+            const double o = __shfl(a, lane + g, 64);
+            if (sub == 0) total += o;
+        }
+        a = total;
+    }
+    if (!live || sub != 0) return;
+    if (i < 3 * n) {
+        const double r = lam_r[i] + a;
+        lam_r[i] = r;
+        if (drift) lam_v[i] = __builtin_fma(dt, r, lam_v[i]);
+    } else {
+        g_m[i - 3 * n] += a;
     }
 }
 
@@ -197,12 +230,26 @@ static hipError_t vjp_tw(const double* pos, const double* mass, const double* la
     return hipGetLastError();
 }
 
+static constexpr int64_t kVjpGranule = 8;
+
+int64_t vjp_chunk_length(int64_t n, const Tile& t)
+{
+    const int64_t per = (n + t.chunks - 1) / t.chunks;
+    return (per + kVjpGranule - 1) / kVjpGranule * kVjpGranule;
+}
+
+int vjp_chunks(int64_t n, const Tile& t)
+{
+    const int64_t L = vjp_chunk_length(n, t);
+    return (int)((n + L - 1) / L);
+}
+
 hipError_t launch_vjp(const Tile& tile, const double* pos, const double* mass, const double* lam,
                       double cu, int64_t n, double G, double* part, hipStream_t s)
 {
     if (tile.variant != 0) return hipErrorInvalidValue;
-    const int64_t L = chunk_length(n, tile);
-    const int chunks = (int)((n + L - 1) / L);
+    const int64_t L = vjp_chunk_length(n, tile);
+    const int chunks = vjp_chunks(n, tile);
 #define NB_CASE(TT, WW)                                                                 \
     if (tile.tpl == TT && tile.waves == WW)                                             \
         return vjp_tw<TT, WW>(pos, mass, lam, cu, n, L, chunks, G, part, s);
@@ -214,8 +261,12 @@ hipError_t launch_vjp(const Tile& tile, const double* pos, const double* mass, c
 hipError_t launch_vjp_reduce(const double* part, int chunks, int64_t n, double* lam_r,
                              double* g_m, double* lam_v, double dt, bool drift, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_vjp_reduce, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, part,
-                       chunks, n, lam_r, g_m, lam_v, dt, drift ? 1 : 0);
+    if (chunks >= 16)
+        hipLaunchKernelGGL(k_vjp_reduce<4>, dim3(blocks_for(16 * n, kBlock)), dim3(kBlock), 0, s,
+                           part, chunks, n, lam_r, g_m, lam_v, dt, drift ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_vjp_reduce<1>, dim3(blocks_for(4 * n, kBlock)), dim3(kBlock), 0, s,
+                           part, chunks, n, lam_r, g_m, lam_v, dt, drift ? 1 : 0);
     return hipGetLastError();
 }
 

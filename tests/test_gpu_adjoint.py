@@ -54,6 +54,25 @@ def test_adjoint_matches_oracle(steps, K, tile):
     nb.reset_caches()
 
 
+@pytest.mark.parametrize("vtile", [(1, 1, 1, 0), (2, 1, 3, 0), (1, 4, 5, 0), (2, 2, 64, 0),
+                                   (1, 1, 64, 0), (1, 2, 17, 0)])
+@pytest.mark.parametrize("n_small", [20, 150])
+def test_adjoint_transpose_pass_tiles(vtile, n_small):
+    """The transpose-Jacobian pass over tile shapes and source chunkings
+    (chunks of multiples of 8 sources, partly used LDS tiles)."""
+    nb.reset_caches()
+    s = S.solar_system(43, n_small, n_major=19)
+    nb.set_tile(1, "fp64", s.n, *vtile)
+    rng = np.random.default_rng(n_small)
+    lr, lv = rng.normal(size=(3, s.n)), rng.normal(size=(3, s.n)) * 10
+    gr, gv, gm = oracle.adjoint(s.pos, s.vel, s.mass, s.G, 0.1, 30, lr, lv)
+    Gr, Gv, Gm, _, _ = nb.verlet_adjoint(T(s.pos), T(s.vel), T(s.mass), s.G, 0.1, 30, 7, T(lr), T(lv))
+    er, ev, em = nrel(H(Gr), gr), nrel(H(Gv), gv), nrel(H(Gm), gm)
+    print(f"n={s.n} vtile={vtile}: rel err r0 {er:.2e} v0 {ev:.2e} m {em:.2e}", flush=True)
+    assert er <= 1e-10 and ev <= 1e-10 and em <= 1e-10
+    nb.reset_caches()
+
+
 def test_adjoint_zero_steps_is_identity():
     s = S.solar_system(42, 5, n_major=3)
     lr, lv = np.ones((3, s.n)), 2 * np.ones((3, s.n))
