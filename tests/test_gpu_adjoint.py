@@ -73,6 +73,27 @@ def test_adjoint_transpose_pass_tiles(vtile, n_small):
     nb.reset_caches()
 
 
+def test_adjoint_full_size_prefix_matches_oracle():
+    """The 2,079-body adjoint workload at full size in the benchmark's launch
+    configuration (default tiles, checkpoints every 100 steps, ragged last
+    segment), over a 150-step prefix, against the oracle's reverse sweep."""
+    nb.reset_caches()
+    s = S.config(4)
+    steps = 150
+    first = 1 + s.counts["major"]
+    rng = np.random.default_rng(250)
+    lr = np.zeros((3, s.n))
+    lr[:, first:] = rng.normal(size=(3, s.n - first)) * 1e-8
+    lv = np.zeros((3, s.n))
+    gr, gv, gm = oracle.adjoint(s.pos, s.vel, s.mass, s.G, s.dt, steps, lr, lv)
+    Gr, Gv, Gm, _, _ = nb.verlet_adjoint(T(s.pos), T(s.vel), T(s.mass), s.G, s.dt, steps, 100,
+                                         T(lr), T(lv))
+    er, ev, em = nrel(H(Gr), gr), nrel(H(Gv), gv), nrel(H(Gm)[1:31], gm[1:31])
+    print(f"n={s.n}, {steps} steps: rel err r0 {er:.2e} v0 {ev:.2e} major masses {em:.2e}",
+          flush=True)
+    assert er <= 1e-10 and ev <= 1e-10 and em <= 1e-10
+
+
 def test_adjoint_zero_steps_is_identity():
     s = S.solar_system(42, 5, n_major=3)
     lr, lv = np.ones((3, s.n)), 2 * np.ones((3, s.n))

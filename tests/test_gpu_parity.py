@@ -396,6 +396,32 @@ def test_batched_autotune_then_parity(precision):
         assert rel(P[:, offs[k]:offs[k + 1]], pr) <= (1e-12 if precision == "fp64" else 1e-10)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_batched_full_ensemble_sampled(precision):
+    """The 512-system ensemble at full size, in the launch configuration the
+    benchmark times (autotuned tile, one batched launch per step), against
+    the oracle on the smallest, the largest and two random member systems."""
+    systems, offs = S.ensemble(512)
+    cat = lambda f: np.ascontiguousarray(np.concatenate([f(x) for x in systems], axis=-1))
+    pos, vel, mass = cat(lambda x: x.pos), cat(lambda x: x.vel), cat(lambda x: x.mass)
+    p, v, m = T(pos), T(vel), T(mass)
+    tile, _ = nb.autotune_batched(p, m, offs, S.G_AU_DAY_MSUN, precision)
+    steps = 3
+    nb.verlet_run_batched(p, v, m, offs, S.G_AU_DAY_MSUN, 0.1, steps, precision=precision)
+    P, V = H(p), H(v)
+    sizes = np.diff(offs)
+    rng = np.random.default_rng(11)
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), *rng.choice(512, 2, replace=False)})
+    for k in pick:
+        x = systems[k]
+        pr, vr = oracle.verlet(x.pos, x.vel, x.mass, x.G, 0.1, steps)
+        a, b = offs[k], offs[k + 1]
+        ep, ev = rel(P[:, a:b], pr), rel(V[:, a:b], vr)
+        log(f"ensemble {precision} tile {tile} system {k} (n={x.n}): pos {ep:.2e} vel {ev:.2e}")
+        assert ep <= (1e-12 if precision == "fp64" else 1e-10)
+        assert ev <= (1e-11 if precision == "fp64" else 1e-9)
+
+
 def test_batched_graph_replay_deterministic():
     systems, offs, pos, vel, mass = _small_ensemble(count=4)
     outs = []
