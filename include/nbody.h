@@ -24,8 +24,11 @@
  *   - Ownership: the caller owns every buffer.  Scratch memory is the
  *     caller's `workspace` of at least nbody_workspace_bytes(...) bytes
  *     (256-byte aligned); the library allocates no device memory.  It keeps
- *     only its tile-shape table and captured step graphs, both released by
- *     nbody_reset_caches().
+ *     only its tile-shape table, up to 64 captured step graphs and up to 8
+ *     ensemble work lists (least recently used dropped first, after waiting
+ *     for the device), all released by nbody_reset_caches().  A captured
+ *     graph bakes in the addresses of the buffers it ran on; a later call
+ *     with the same buffers replays it.
  *   - Errors: arguments are validated before anything is enqueued; a bad
  *     argument returns NBODY_EINVAL (nothing enqueued), a short workspace
  *     NBODY_EWORKSPACE, a HIP failure NBODY_EHIP.  nbody_last_error() gives
@@ -198,7 +201,8 @@ int32_t nbody_time_force(int32_t kind, int32_t precision, const double* pos, con
                          void* workspace, size_t workspace_bytes, void* stream,
                          double* ms_per_pass_host);
 
-/* Drops captured graphs and tuned tile shapes. */
+/* Drops captured graphs, ensemble work lists and tuned tile shapes; waits
+ * for the devices those graphs ran on first. */
 void nbody_reset_caches(void);
 
 /* Message describing the calling thread's last failure ("" if none). */

@@ -256,16 +256,34 @@ struct GraphKey {
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    int device = 0;
+    uint64_t used = 0;   // last use (for eviction)
 };
 
+// Captured graphs, keyed by everything they bake in (device, sizes, scalars,
+// buffer addresses).  At most kMaxGraphs are kept; the least recently used
+// one is dropped first.  g_graph_mu serialises capture, lookup and launch.
+constexpr size_t kMaxGraphs = 64;
+std::mutex g_graph_mu;
 std::map<GraphKey, GraphEntry> g_graphs;
+uint64_t g_graph_tick = 0;
+
+// A graph may still be running when it is dropped: wait for its device first.
+void destroy_graph(const GraphEntry& e)
+{
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(e.device) == hipSuccess) {
+        (void)hipDeviceSynchronize();
+        (void)hipSetDevice(cur);
+    }
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+}
 
 void drop_graphs()
 {
-    for (auto& kv : g_graphs) {
-        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
-        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
-    }
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto& kv : g_graphs) destroy_graph(kv.second);
     g_graphs.clear();
 }
 
@@ -280,18 +298,18 @@ uint64_t bits(double x)
 
 uint64_t ptrbits(const void* p) { return (uint64_t)reinterpret_cast<uintptr_t>(p); }
 
-// Captures `body(stream)` once per key and launches the instantiated graph on
-// `stream`.  body must only enqueue kernels.
+// Captures `body(stream)` once per key (plus the current device) and launches
+// the instantiated graph on `stream`.  body must only enqueue kernels.
 template <typename F>
-int run_graph(const GraphKey& key, hipStream_t stream, F&& body)
+int run_graph(const GraphKey& key_in, hipStream_t stream, F&& body)
 {
-    hipGraphExec_t exec = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        auto it = g_graphs.find(key);
-        if (it != g_graphs.end()) exec = it->second.exec;
-    }
-    if (!exec) {
+    int dev = 0;
+    NB_HIP(hipGetDevice(&dev));
+    GraphKey key = key_in;
+    key.v.push_back((uint64_t)dev);
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it == g_graphs.end()) {
         hipStream_t cs = nullptr;
         NB_TRY(capture_stream(&cs));
         NB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
@@ -309,14 +327,21 @@ int run_graph(const GraphKey& key, hipStream_t stream, F&& body)
             (void)hipGraphDestroy(g);
             return fail(NBODY_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
         }
-        std::lock_guard<std::mutex> lk(g_mu);
+        while (g_graphs.size() >= kMaxGraphs) {
+            auto victim = g_graphs.begin();
+            for (auto jt = g_graphs.begin(); jt != g_graphs.end(); ++jt)
+                if (jt->second.used < victim->second.used) victim = jt;
+            destroy_graph(victim->second);
+            g_graphs.erase(victim);
+        }
         GraphEntry e;
         e.graph = g;
         e.exec = ge;
-        g_graphs[key] = e;
-        exec = ge;
+        e.device = dev;
+        it = g_graphs.emplace(key, e).first;
     }
-    NB_HIP(hipGraphLaunch(exec, stream));
+    it->second.used = ++g_graph_tick;
+    NB_HIP(hipGraphLaunch(it->second.exec, stream));
     return NBODY_OK;
 }
 
@@ -634,9 +659,9 @@ int32_t nbody_set_tile(int32_t kind, int32_t precision, int64_t n, const nbody_t
 
 void nbody_reset_caches(void)
 {
+    drop_graphs();
     std::lock_guard<std::mutex> lk(g_mu);
     g_tiles.clear();
-    drop_graphs();
     drop_batch_plans();
 }
 
@@ -800,9 +825,20 @@ struct BatchPlan {
     std::vector<int64_t> offsets;
 };
 
+// Work lists of recent ensembles (host memory; uploaded each run).  At most
+// kMaxBatchPlans are kept, the least recently used dropped first.
+constexpr size_t kMaxBatchPlans = 8;
 std::map<std::vector<int64_t>, std::shared_ptr<BatchPlan>> g_batch;
+std::map<std::vector<int64_t>, uint64_t> g_batch_used;
+uint64_t g_batch_tick = 0;
 
-void drop_batch_plans() { g_batch.clear(); }
+void drop_batch_plans()
+{
+    // uploads of a plan read its host vectors asynchronously
+    (void)hipDeviceSynchronize();
+    g_batch.clear();
+    g_batch_used.clear();
+}
 
 constexpr int64_t kBatchChunkLen = 1024;   // sources per chunk in the ensemble
 
@@ -813,8 +849,18 @@ std::shared_ptr<BatchPlan> batch_plan(const int64_t* offs, int32_t ns, const Til
     key.push_back(t.waves);
     key.push_back(t.variant);
     std::lock_guard<std::mutex> lk(g_mu);
+    g_batch_used[key] = ++g_batch_tick;
     auto it = g_batch.find(key);
     if (it != g_batch.end()) return it->second;
+    if (g_batch.size() >= kMaxBatchPlans) {
+        // uploads of the dropped plan read its host vectors asynchronously
+        (void)hipDeviceSynchronize();
+        auto victim = g_batch.begin();
+        for (auto jt = g_batch.begin(); jt != g_batch.end(); ++jt)
+            if (g_batch_used[jt->first] < g_batch_used[victim->first]) victim = jt;
+        g_batch_used.erase(victim->first);
+        g_batch.erase(victim);
+    }
     auto bp = std::make_shared<BatchPlan>();
     bp->offsets.assign(offs, offs + ns + 1);
     const int64_t n_total = offs[ns];
@@ -857,14 +903,6 @@ int device_cus(int* cus)
     NB_HIP(hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev));
     return NBODY_OK;
 }
-
-}  // namespace
-
-extern "C" {
-
-}  // extern "C"
-
-namespace {
 
 int check_offsets(const int64_t* offsets_host, int32_t num_systems)
 {

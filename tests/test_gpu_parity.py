@@ -239,6 +239,29 @@ def test_split_class_boundaries(threshold, tol_sun, tol, tile):
     assert rel(P[:, :1], pr[:, :1]) <= sun_tol and rel(P[:, 1:], pr[:, 1:]) <= run_tol
 
 
+def test_graph_cache_eviction():
+    """More distinct buffer sets than the library keeps step graphs for (64):
+    older graphs are dropped and recaptured, results stay bit-identical."""
+    s = S.solar_system(17, 269, n_major=30)   # n = 300: the multi-kernel path, graphs
+    m = T(s.mass)
+    steps = 2 * 64 + 3                        # at least one graph replay per run
+    keep, outs = [], []
+    for k in range(70):
+        p, v = T(s.pos), T(s.vel)             # new buffers each time: a new graph key
+        nb.verlet_run(p, v, m, s.G, 0.1, steps)
+        keep.append((p, v))
+        if k in (0, 69):
+            outs.append(H(p))
+    p, v = keep[0]
+    p.copy_(T(s.pos))
+    v.copy_(T(s.vel))
+    nb.verlet_run(p, v, m, s.G, 0.1, steps)   # its graph was evicted: recaptured
+    outs.append(H(p))
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    pr, _ = oracle.verlet(s.pos, s.vel, s.mass, s.G, 0.1, steps)
+    assert rel(outs[0], pr) <= 1e-12
+
+
 def test_verlet_zero_steps_is_noop():
     s = S.config(0)
     p, v = T(s.pos), T(s.vel)
