@@ -155,7 +155,11 @@ int32_t nbody_get_flags(void* workspace, void* stream, int32_t clear, int32_t* f
  * one workgroup holds the system in LDS and runs whole steps, force pass,
  * reduction and kick-drift-kick, in one launch; chunks is then the number
  * of source slices per target (capped at 1024 / n).  The heuristic picks it
- * for n <= 192. */
+ * for n <= 160.
+ * Variant 4 (kind 0 only, targets_per_lane 1 or 2, waves 2, 4 or 8, chunks
+ * 1): the waves of a workgroup split all sources of its targets, and the
+ * same kernel applies the step's kicks and drift, so a step is one launch.
+ * The heuristic picks it for 160 < n <= 512. */
 typedef struct {
     int32_t targets_per_lane;
     int32_t waves;

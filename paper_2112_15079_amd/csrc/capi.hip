@@ -75,13 +75,17 @@ int chunk_cap(int64_t n)
 }
 
 // Systems up to this size default to the single-workgroup variant; up to
-// kShareDefault, to one workgroup of 8 waves per 64 targets (variant 2).
-constexpr int64_t kSmallDefault = 192;
-constexpr int64_t kShareDefault = 288;
+// kFusedDefault, to the fused force-and-step kernel with 8 waves per 64
+// targets (variant 4).
+constexpr int64_t kSmallDefault = 160;
+constexpr int64_t kFusedDefault = 512;
+// The autotuner tries the fused force-and-step kernel up to this size.
+constexpr int64_t kFusedMax = 16384;
 
 // Defaults from tile sweeps on MI355X (the autotuner refines them): one
 // workgroup running whole steps for small systems (as many source slices as
-// 1024 lanes allow, at most 16); otherwise about 8192 wavefronts in flight;
+// 1024 lanes allow, at most 16); then one kernel per step with 8 waves
+// sharing each 64 targets; otherwise about 8192 wavefronts in flight;
 // scalar-operand sources for FP64 below ~3e4 bodies, LDS tiles with 4
 // targets per lane above; the split form prefers the LDS tiles at every size.
 Tile heuristic_tile(int kind, int prec, int64_t n)
@@ -89,7 +93,7 @@ Tile heuristic_tile(int kind, int prec, int64_t n)
     if (kind == 2) return Tile{2, 1, kBatchChunkMax, 0};   // ensemble: per-system chunks
     if (kind == 0 && n <= kSmallDefault)
         return Tile{1, 16, (int)std::max<int64_t>(1, std::min<int64_t>(16, 1024 / n)), 3};
-    if (kind == 0 && n <= kShareDefault) return Tile{1, 8, 1, 2};
+    if (kind == 0 && n <= kFusedDefault) return Tile{1, 8, 1, 4};
     if (kind == 1) {
         // transpose-Jacobian pass: one wave per 64 targets, sources split in
         // chunks of >= 16 until about 4096 waves are in flight
@@ -379,19 +383,29 @@ int force(const StepPlan& P, const double* pos, hipStream_t s)
     return NBODY_OK;
 }
 
+// The force pass at pin followed by the epilogue in `mode` (one fused kernel
+// for a variant-4 tile).
+int force_and_step(const StepPlan& P, const double* pin, double* pout, int mode, hipStream_t s)
+{
+    if (P.tile.variant == 4 && !P.units) {
+        NB_HIP(launch_step_fused(P.prec, P.tile, pin, pout, P.vel, P.gm, P.n, P.nmaj, P.dt, mode,
+                                 nullptr, P.flags, s));
+        return NBODY_OK;
+    }
+    NB_TRY(force(P, pin, s));
+    NB_HIP(launch_step(P.part, P.chunks, P.bchunks, P.n, P.vel, pin, pout, nullptr, P.dt, mode,
+                       P.flags, s));
+    return NBODY_OK;
+}
+
 // Launch i of a run of `steps` steps (i = 0 .. steps): the force pass at r_i
 // (in buf[i & 1]) followed by the epilogue.
 int step_launch(const StepPlan& P, int64_t i, int64_t steps, hipStream_t s)
 {
-    const double* pin = P.buf[i & 1];
-    double* pout = P.buf[(i + 1) & 1];
-    NB_TRY(force(P, pin, s));
     int mode = 0;
     if (i > 0) mode |= kClose;
     if (i < steps) mode |= kOpen;
-    NB_HIP(launch_step(P.part, P.chunks, P.bchunks, P.n, P.vel, pin, pout, nullptr, P.dt, mode,
-                       P.flags, s));
-    return NBODY_OK;
+    return force_and_step(P, P.buf[i & 1], P.buf[(i + 1) & 1], mode, s);
 }
 
 constexpr int64_t kGraphSteps = 64;   // middle steps per captured graph (even)
@@ -477,6 +491,7 @@ int32_t nbody_accel(const double* pos, const double* vel, const double* mass, in
     uint32_t* flags = at<uint32_t>(workspace, L.flags);
     double* gm = at<double>(workspace, L.gm);
     const bool small = tile.variant == 3;
+    const bool fused = tile.variant == 4;
     if (precision == NBODY_FP64) {
         if (small) {
             NB_HIP(launch_run_small(0, tile, pos, nullptr, nullptr, mass, n, nullptr, G, 0.0, 0, 0,
@@ -484,6 +499,11 @@ int32_t nbody_accel(const double* pos, const double* vel, const double* mass, in
             return NBODY_OK;
         }
         NB_HIP(launch_scale(mass, G, n, gm, s));
+        if (fused) {
+            NB_HIP(launch_step_fused(0, tile, pos, nullptr, nullptr, gm, n, nullptr, 0.0, kStoreAcc,
+                                     acc_out, flags, s));
+            return NBODY_OK;
+        }
         NB_HIP(launch_force(0, tile, pos, mass, gm, n, nullptr, G, part, s));
         NB_HIP(launch_step(part, chunks, nullptr, n, nullptr, nullptr, nullptr, acc_out, 0.0,
                            kStoreAcc, flags, s));
@@ -500,6 +520,10 @@ int32_t nbody_accel(const double* pos, const double* vel, const double* mass, in
         NB_HIP(launch_run_small(1, tile, pos_c, nullptr, nullptr, mass_c, n,
                                 at<int64_t>(workspace, L.nmaj), G, 0.0, 0, 0, 0, acc_c, nullptr,
                                 flags, s));
+    } else if (fused) {
+        NB_HIP(launch_scale(mass_c, G, n, gm, s));
+        NB_HIP(launch_step_fused(1, tile, pos_c, nullptr, nullptr, gm, n,
+                                 at<int64_t>(workspace, L.nmaj), 0.0, kStoreAcc, acc_c, flags, s));
     } else {
         NB_HIP(launch_scale(mass_c, G, n, gm, s));
         NB_HIP(launch_force(1, tile, pos_c, mass_c, gm, n, at<int64_t>(workspace, L.nmaj), G, part,
@@ -650,7 +674,7 @@ int32_t nbody_set_tile(int32_t kind, int32_t precision, int64_t n, const nbody_t
     if (kind == 2) n = 0;
     Tile t{tile_host->targets_per_lane, tile_host->waves, tile_host->chunks, tile_host->variant};
     if (!tile_supported(t) || (kind == 1 && (t.tpl > 2 || t.waves > 4 || t.variant != 0)) ||
-        (t.variant == 3 && (kind != 0 || n > kSmallMax)))
+        (t.variant == 3 && (kind != 0 || n > kSmallMax)) || (t.variant == 4 && kind != 0))
         return fail(NBODY_EINVAL, "unsupported tile (%d, %d, %d)", t.tpl, t.waves, t.chunks);
     std::lock_guard<std::mutex> lk(g_mu);
     g_tiles[std::make_tuple(kind, precision, size_class(n))] = t;
@@ -792,10 +816,7 @@ int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const doubl
                                         kseg - 2, kseg, nullptr, seg + 3 * n, flags, cs));
             for (int64_t k = 0; !small && k + 1 < kseg; ++k) {
                 double* pin = seg + k * 3 * n;
-                NB_TRY(force(R, pin, cs));
-                const int mode = (k > 0 ? kClose : 0) | kOpen;
-                NB_HIP(launch_step(part, R.chunks, nullptr, n, vtmp, pin, pin + 3 * n, nullptr, dt,
-                                   mode, flags, cs));
+                NB_TRY(force_and_step(R, pin, pin + 3 * n, (k > 0 ? kClose : 0) | kOpen, cs));
             }
             for (int64_t k = kseg - 1; k >= 0; --k) {
                 const int64_t i = c * K + k;
@@ -1165,6 +1186,9 @@ int32_t nbody_time_force(int32_t kind, int32_t precision, const double* pos, con
         if (kind == 0 && t.variant == 3)
             NB_HIP(launch_run_small(precision, t, b.pos, nullptr, nullptr, b.mass, n, b.nmaj, G, 0.0,
                                     0, 0, 0, b.scratch, nullptr, nullptr, s));
+        else if (kind == 0 && t.variant == 4)
+            NB_HIP(launch_step_fused(precision, t, b.pos, nullptr, nullptr, b.gm, n, b.nmaj, 0.0,
+                                     kStoreAcc, b.scratch, nullptr, s));
         else if (kind == 0)
             NB_HIP(launch_force(precision, t, b.pos, b.mass, b.gm, n, b.nmaj, G, b.part, s));
         else           NB_HIP(launch_vjp(t, b.pos, b.mass, b.scratch, 1.0, n, G, b.part, s));
@@ -1230,6 +1254,11 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
             }
         }
 
+    if (kind == 0 && n <= kFusedMax) {
+        // force pass and step in one kernel, waves of a group splitting the sources
+        for (int tpl : {1, 2})
+            for (int w : {2, 4, 8}) cands.push_back(Tile{tpl, w, 1, 4});
+    }
     if (kind == 0 && n <= kSmallMax) {
         // single workgroup: force pass, reduction and store in one launch
         for (int S : {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 16, 24, 32, 48, 64}) {
@@ -1252,6 +1281,9 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
             NB_HIP(launch_run_small(precision, t, r_small, r_small, v_small, mass_w, n, nmaj, G,
                                     0.0, 0, kSmallPasses - 1, kSmallPasses, nullptr, nullptr,
                                     nullptr, s));
+        } else if (kind == 0 && t.variant == 4) {
+            NB_HIP(launch_step_fused(precision, t, pos_w, nullptr, nullptr, b.gm, n, nmaj, 0.0,
+                                     kStoreAcc, scratch, nullptr, s));
         } else if (kind == 0) {
             NB_HIP(launch_force(precision, t, pos_w, mass_w, b.gm, n, nmaj, G, part, s));
             NB_HIP(launch_step(part, effective_chunks(n, t), nullptr, n, nullptr, nullptr, nullptr,

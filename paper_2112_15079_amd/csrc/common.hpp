@@ -20,7 +20,9 @@ struct Tile {
     int variant = 0;  // 0: sources staged in LDS; 1: sources as scalar operands;
                       // 2: as 1, with the waves of a group splitting the sources;
                       // 3: one workgroup runs whole steps (n <= kSmallMax, tpl = 1,
-                      //    waves = 16, chunks = source slices per target)
+                      //    waves = 16, chunks = source slices per target);
+                      // 4: as 2 over all sources (chunks = 1) with the step's kicks
+                      //    and drift in the same kernel (tpl 1, 2; waves 2, 4, 8)
 };
 
 constexpr int kMaxChunks = 64;
@@ -95,6 +97,13 @@ enum StepMode : int {
     kClose = 2,      // v += dt/2 a  (closing half kick of the step that ends here)
     kOpen = 4,       // v += dt/2 a; r_out = r_in + dt v  (next step's kick + drift)
 };
+
+// One launch of the step loop with a variant-4 tile: Eq. (1) at pos_in and
+// the mode's updates, in one kernel (pos_out != pos_in).
+hipError_t launch_step_fused(int precision, const Tile& tile, const double* pos_in,
+                             double* pos_out, double* vel, const double* gm, int64_t n,
+                             const int64_t* nmaj, double dt, int mode, double* acc,
+                             uint32_t* flags, hipStream_t s);
 // a_p = sum_{c < chunks_of(p)} part[c][.][p] in ascending c, then the mode's
 // updates.  chunks_of(p) = chunks, or body_chunks[p] when that is not NULL.
 hipError_t launch_step(const double* part, int chunks, const int8_t* body_chunks, int64_t n,

@@ -295,12 +295,13 @@ __device__ __forceinline__ void kahan_flush(Kahan<T>& k, float (&bx)[T], float (
 // all waves share the targets [tb0, tb0 + 64*T) (lane l holds tb0 + t*64 + l)
 // and split the sources into W contiguous runs; the W partial sums are added
 // in wave order through LDS, so one partial per group reaches global memory.
-template <int T, int W, bool SPLIT, bool SHARE>
+// out(comp, p, a) receives the sum over [jbeg, jend) of component comp of
+// target p's acceleration, once per (comp, p < n).
+template <int T, int W, bool SPLIT, bool SHARE, class Out>
 __device__ __forceinline__ void force_block_s(const double* __restrict__ pos,
                                               const double* __restrict__ gm, int64_t stride,
                                               int64_t n, int64_t n_major, int64_t tb0,
-                                              int64_t jbeg, int64_t jend,
-                                              double* __restrict__ part_c)
+                                              int64_t jbeg, int64_t jend, Out&& out)
 {
     constexpr int TS = SHARE ? 64 : 64 * W;   // stride between a lane's targets
     const int lane = SHARE ? (threadIdx.x & 63) : threadIdx.x;
@@ -408,20 +409,30 @@ __device__ __forceinline__ void force_block_s(const double* __restrict__ pos,
             for (int w = 1; w < W; ++w) s += red[w][row][lane];
             const int t = row / 3, comp = row % 3;
             const int64_t p = tb0 + (int64_t)t * 64 + lane;
-            if (p < n) part_c[comp * stride + p] = s;
+            if (p < n) out(comp, p, s);
         }
     } else {
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             const int64_t p = tb0 + (int64_t)t * TS + lane;
             if (p < n) {
-                part_c[p] = ax[t];
-                part_c[stride + p] = ay[t];
-                part_c[2 * stride + p] = az[t];
+                out(0, p, ax[t]);
+                out(1, p, ay[t]);
+                out(2, p, az[t]);
             }
         }
     }
 }
+
+// Store into the chunk-partial planes (plane stride `stride`).
+struct PartStore {
+    double* __restrict__ part_c;
+    int64_t stride;
+    __device__ __forceinline__ void operator()(int comp, int64_t p, double a) const
+    {
+        part_c[comp * stride + p] = a;
+    }
+};
 
 template <int T, int W, bool SPLIT, bool SHARE>
 __global__ __launch_bounds__(64 * W) void k_force_s(const double* __restrict__ pos,
@@ -434,7 +445,54 @@ __global__ __launch_bounds__(64 * W) void k_force_s(const double* __restrict__ p
     const int64_t c = blockIdx.y;
     const int64_t jbeg = c * chunk_len;
     const int64_t jend = (jbeg + chunk_len < n) ? jbeg + chunk_len : n;
-    force_block_s<T, W, SPLIT, SHARE>(pos, gm, n, n, n_major, tb0, jbeg, jend, part + c * 3 * n);
+    force_block_s<T, W, SPLIT, SHARE>(pos, gm, n, n, n_major, tb0, jbeg, jend,
+                                      PartStore{part + c * 3 * n, n});
+}
+
+// Whole step in one launch (variant 4): the waves of a workgroup split all n
+// sources of its 64*T targets (as variant 2 with a single chunk), reduce
+// through LDS in wave order, and the same threads apply the step's kicks and
+// drift (the arithmetic of k_step for one chunk).  pos_in and pos_out are
+// different buffers.
+struct StepKdk {
+    const double* __restrict__ pos_in;
+    double* __restrict__ pos_out;
+    double* __restrict__ vel;
+    double* __restrict__ acc;
+    uint32_t* __restrict__ flags;
+    int64_t n;
+    double hdt, dt;
+    int mode;
+    __device__ __forceinline__ void operator()(int comp, int64_t p, double a) const
+    {
+        const int64_t e = comp * n + p;
+        bool finite = __builtin_isfinite(a);
+        if (mode & kStoreAcc) acc[e] = a;
+        if (mode & (kClose | kOpen)) {
+            double v = vel[e];
+            if (mode & kClose) v = v + hdt * a;
+            if (mode & kOpen) {
+                v = v + hdt * a;
+                const double r = pos_in[e] + dt * v;
+                finite = finite && __builtin_isfinite(r);
+                pos_out[e] = r;
+            }
+            finite = finite && __builtin_isfinite(v);
+            vel[e] = v;
+        }
+        if (!finite && flags) atomicOr(flags, 1u);
+    }
+};
+
+template <int T, int W, bool SPLIT>
+__global__ __launch_bounds__(64 * W) void k_step_fused(const double* __restrict__ pos_in,
+                                                       const double* __restrict__ gm, int64_t n,
+                                                       const int64_t* __restrict__ nmaj,
+                                                       StepKdk kdk)
+{
+    const int64_t n_major = SPLIT ? nmaj[0] : 0;
+    const int64_t tb0 = (int64_t)blockIdx.x * 64 * T;
+    force_block_s<T, W, SPLIT, true>(pos_in, gm, n, n, n_major, tb0, 0, n, kdk);
 }
 
 template <int T, int W, bool SPLIT, bool SHARE>
@@ -457,7 +515,8 @@ __global__ __launch_bounds__(64 * W) void k_force_s_batched(const double* __rest
         const int64_t tb0 = (int64_t)w.tblock * (SHARE ? 64 : 64 * W) * T;
         force_block_s<T, W, SPLIT, SHARE>(pos + w.body0, gm + w.body0, n_total, n, n_major, tb0,
                                           jbeg, jend,
-                                          part + (int64_t)w.chunk * 3 * n_total + w.body0);
+                                          PartStore{part + (int64_t)w.chunk * 3 * n_total + w.body0,
+                                                    n_total});
         if (SHARE && W > 1) __syncthreads();   // the LDS reduction buffer is reused
     }
 }
@@ -511,6 +570,9 @@ __global__ __launch_bounds__(64 * W) void k_force_batched(const double* __restri
 bool tile_supported(const Tile& t)
 {
     if (t.variant == 3) return t.tpl == 1 && t.waves == 16 && t.chunks >= 1 && t.chunks <= kMaxChunks;
+    if (t.variant == 4)   // (16 waves of 64 would exceed the register file: spills)
+        return (t.tpl == 1 || t.tpl == 2) && (t.waves == 2 || t.waves == 4 || t.waves == 8) &&
+               t.chunks == 1;
     const bool tpl_ok = t.tpl == 1 || t.tpl == 2 || t.tpl == 4;
     const bool w_ok = t.waves == 1 || t.waves == 2 || t.waves == 4 || t.waves == 8;
     return tpl_ok && w_ok && t.chunks >= 1 && t.chunks <= kMaxChunks &&
@@ -519,6 +581,7 @@ bool tile_supported(const Tile& t)
 
 int64_t chunk_length(int64_t n, const Tile& t)
 {
+    if (t.variant == 4) return n;
     if (t.variant == 3) {
         const int64_t S = small_slices(n, t) < 1 ? 1 : small_slices(n, t);
         return (n + S - 1) / S;
@@ -606,7 +669,7 @@ hipError_t launch_force(int precision, const Tile& tile, const double* pos, cons
                         const double* gm, int64_t n, const int64_t* nmaj, double G, double* part,
                         hipStream_t s)
 {
-    if ((tile.variant != 0 && !gm) || tile.variant == 3) return hipErrorInvalidValue;
+    if ((tile.variant != 0 && !gm) || tile.variant >= 3) return hipErrorInvalidValue;
     const int64_t L = chunk_length(n, tile);
     const int chunks = effective_chunks(n, tile);
 #define NB_CASE(TT, WW)                                                                  \
@@ -623,12 +686,43 @@ hipError_t launch_force_batched(int precision, const Tile& tile, const double* p
                                 const BatchUnit* units, int64_t num_units, const int64_t* nmaj,
                                 int grid, double* part, hipStream_t s)
 {
-    if ((tile.variant != 0 && !gm) || tile.variant == 3) return hipErrorInvalidValue;
+    if ((tile.variant != 0 && !gm) || tile.variant >= 3) return hipErrorInvalidValue;
 #define NB_CASE(TT, WW)                                                                   \
     if (tile.tpl == TT && tile.waves == WW)                                               \
         return launch_batched_tw<TT, WW>(precision, tile.variant, pos, mass, gm, n_total, G, \
                                          units, num_units, nmaj, grid, part, s);
     NB_TILE_CASES(NB_CASE)
+#undef NB_CASE
+    return hipErrorInvalidValue;
+}
+
+template <int T, int W>
+static hipError_t step_fused_tw(int precision, const double* pos_in, const double* gm, int64_t n,
+                                const int64_t* nmaj, const StepKdk& kdk, hipStream_t s)
+{
+    const dim3 grid((unsigned)((n + 64 * T - 1) / (64 * T)));
+    if (precision == 0)
+        hipLaunchKernelGGL((k_step_fused<T, W, false>), grid, dim3(64 * W), 0, s, pos_in, gm, n,
+                           nmaj, kdk);
+    else
+        hipLaunchKernelGGL((k_step_fused<T, W, true>), grid, dim3(64 * W), 0, s, pos_in, gm, n,
+                           nmaj, kdk);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_fused(int precision, const Tile& tile, const double* pos_in,
+                             double* pos_out, double* vel, const double* gm, int64_t n,
+                             const int64_t* nmaj, double dt, int mode, double* acc,
+                             uint32_t* flags, hipStream_t s)
+{
+    if (tile.variant != 4 || !gm || (precision == 1 && !nmaj) ||
+        ((mode & kStoreAcc) && !acc) || ((mode & (kClose | kOpen)) && !vel) ||
+        ((mode & kOpen) && (!pos_out || pos_out == pos_in)))
+        return hipErrorInvalidValue;
+    const StepKdk kdk{pos_in, pos_out, vel, acc, flags, n, 0.5 * dt, dt, mode};
+#define NB_CASE(TT, WW) \
+    if (tile.tpl == TT && tile.waves == WW) return step_fused_tw<TT, WW>(precision, pos_in, gm, n, nmaj, kdk, s);
+    NB_CASE(1, 2) NB_CASE(1, 4) NB_CASE(1, 8) NB_CASE(2, 2) NB_CASE(2, 4) NB_CASE(2, 8)
 #undef NB_CASE
     return hipErrorInvalidValue;
 }

@@ -157,7 +157,9 @@ def test_tile_table_single_workgroup_variant():
         assert lib.nbody_get_tile(0, prec, 131, ctypes.byref(t)) == C.NBODY_OK
         # as many slices as 1024 lanes allow: 1024 // 131 = 7
         assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == (1, 16, 7, 3)
-        assert lib.nbody_get_tile(0, prec, 193, ctypes.byref(t)) == C.NBODY_OK and t.variant != 3
+        assert lib.nbody_get_tile(0, prec, 193, ctypes.byref(t)) == C.NBODY_OK
+        assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == (1, 8, 1, 4)
+        assert lib.nbody_get_tile(0, prec, 600, ctypes.byref(t)) == C.NBODY_OK and t.variant < 3
     assert lib.nbody_get_tile(0, 0, 16, ctypes.byref(t)) == C.NBODY_OK and t.chunks == 16
     assert lib.nbody_get_tile(1, 0, 131, ctypes.byref(t)) == C.NBODY_OK and t.variant == 0
     assert lib.nbody_get_tile(2, 0, 0, ctypes.byref(t)) == C.NBODY_OK and t.variant != 3
@@ -171,6 +173,13 @@ def test_tile_table_single_workgroup_variant():
     for bad in [(1, 8, 4, 3), (2, 16, 4, 3), (1, 16, 0, 3), (1, 16, 65, 3), (1, 1, 1, 4)]:
         assert lib.nbody_set_tile(0, 0, 131, ctypes.byref(C.Tile(*bad))) == C.NBODY_EINVAL, bad
     assert lib.nbody_set_tile(1, 0, 131, ctypes.byref(C.Tile(1, 16, 4, 3))) == C.NBODY_EINVAL
+    # variant 4 (force pass and step fused): tpl 1 or 2, waves 2..8, one chunk, kind 0
+    assert lib.nbody_set_tile(0, 0, 3000, ctypes.byref(C.Tile(2, 8, 1, 4))) == C.NBODY_OK
+    assert lib.nbody_get_tile(0, 0, 3000, ctypes.byref(t)) == C.NBODY_OK and t.variant == 4
+    for bad in [(1, 16, 1, 4), (4, 2, 1, 4), (1, 1, 1, 4), (1, 2, 2, 4)]:
+        assert lib.nbody_set_tile(0, 0, 3000, ctypes.byref(C.Tile(*bad))) == C.NBODY_EINVAL, bad
+    assert lib.nbody_set_tile(1, 0, 3000, ctypes.byref(C.Tile(1, 2, 1, 4))) == C.NBODY_EINVAL
+    assert lib.nbody_set_tile(2, 0, 0, ctypes.byref(C.Tile(1, 2, 1, 4))) == C.NBODY_EINVAL
     assert lib.nbody_set_tile(2, 0, 0, ctypes.byref(C.Tile(1, 16, 4, 3))) == C.NBODY_EINVAL
     lib.nbody_reset_caches()
 

@@ -239,10 +239,40 @@ def test_split_class_boundaries(threshold, tol_sun, tol, tile):
     assert rel(P[:, :1], pr[:, :1]) <= sun_tol and rel(P[:, 1:], pr[:, 1:]) <= run_tol
 
 
+FUSED_TILES = [(1, 2, 1, 4), (1, 8, 1, 4), (2, 4, 1, 4), (2, 8, 1, 4)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+@pytest.mark.parametrize("n", [1, 3, 65, 300, 1031])
+def test_fused_step_matches_oracle_and_shared_variant(n, precision):
+    """Force pass and step in one kernel (variant 4): against the oracle, and
+    bit for bit against the shared-target variant with one source chunk
+    followed by the step epilogue (the same sums in the same order)."""
+    s = S.solar_system(60 + n, max(n - 31, 0), n_major=min(30, max(n - 1, 0)))
+    m = T(s.mass)
+    aref = oracle.accel(s.pos, s.mass, s.G)
+    pr, vr = oracle.verlet(s.pos, s.vel, s.mass, s.G, 0.1, 30)
+    atol, ptol = (1e-13, 1e-12) if precision == "fp64" else (2e-12, 1e-10)
+    for t, w, _, _ in FUSED_TILES:
+        out = {}
+        for variant in (4, 2):
+            nb.reset_caches()
+            nb.set_tile(0, precision, s.n, t, w, 1, variant)
+            a = H(nb.accel(T(s.pos), m, s.G, precision=precision))
+            p, v = T(s.pos), T(s.vel)
+            nb.verlet_run(p, v, m, s.G, 0.1, 30, precision=precision)
+            out[variant] = (a, H(p), H(v))
+        a, p, v = out[4]
+        log(f"fused n={s.n} {precision} T={t} W={w}: accel {rel(a, aref):.2e} pos {rel(p, pr):.2e}")
+        assert rel(a, aref) <= atol and rel(p, pr) <= ptol and rel(v, vr) <= 10 * ptol
+        for x, y in zip(out[4], out[2]):
+            assert np.array_equal(x, y)
+
+
 def test_graph_cache_eviction():
     """More distinct buffer sets than the library keeps step graphs for (64):
     older graphs are dropped and recaptured, results stay bit-identical."""
-    s = S.solar_system(17, 269, n_major=30)   # n = 300: the multi-kernel path, graphs
+    s = S.solar_system(17, 269, n_major=30)   # n = 300: graph-replayed steps
     m = T(s.mass)
     steps = 2 * 64 + 3                        # at least one graph replay per run
     keep, outs = [], []
