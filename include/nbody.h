@@ -15,10 +15,10 @@
  *       gradients); mass[0..n).
  *   - Units are the caller's; G must be in those units.  No softening: the
  *     self pair j = p is excluded by index, and two distinct bodies at the
- *     same point give non-finite values, as Eq. (1) does.  Squared
- *     separations must lie inside the FP32 normal range (1e-37 .. 1e37 in
- *     the caller's units), because the reciprocal square root is seeded in
- *     FP32 and refined in FP64.
+ *     same point give non-finite values, as Eq. (1) does.  In the split
+ *     form, squared separations must lie inside the FP32 normal range
+ *     (1e-37 .. 1e37 in the caller's units): its reciprocal square root is
+ *     seeded in FP32 and refined in FP64.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is
  *     enqueued asynchronously on it; results are ready when the stream is.
  *   - Ownership: the caller owns every buffer.  Scratch memory is the

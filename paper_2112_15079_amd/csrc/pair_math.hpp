@@ -7,11 +7,14 @@
 namespace nb {
 namespace pm {
 
-// G m r^-3 to full FP64 accuracy.  The FP32 hardware reciprocal square root
-// y0 (relative error below 2^-22) is exact in FP64 and so is y0^2, hence
-// e = 1 - r2 y0^2 is formed with a single rounding; then
+// G m r^-3 to full FP64 accuracy.  The hardware FP64 reciprocal square root
+// y0 = v_rsq_f64(r2) has a relative error below 2^-24 (measured 2^-24.2), so
+// e = 1 - r2 y0^2 (one FMA; the rounding of y0^2 adds at most 2^-53) is below
+// 2^-23, and
 //   r^-3 = y0^3 (1 - e)^(-3/2) = y0^3 (1 + 3/2 e + 15/8 e^2 + O(e^3)),
-// and the dropped e^3 term is below 1e-18 relative.
+// where the dropped e^3 term is below 1e-20 relative.  (Seeding from the FP32
+// v_rsq_f32 instead makes y0^2 exact but needs two conversions, which cost
+// more than the slower FP64 transcendental in this loop.)
 // c.a = 15/8 and c.b = 3/2 live in vector registers (see vreg_const) so that
 // the polynomial is a single v_fma_f64.
 struct PolyConst {
@@ -20,7 +23,7 @@ struct PolyConst {
 
 static __device__ __forceinline__ double gm_rinv3_f64(double r2, double gm, const PolyConst& c)
 {
-    const double y = (double)__builtin_amdgcn_rsqf((float)r2);
+    const double y = __builtin_amdgcn_rsq(r2);
     const double y2 = y * y;
     const double e = __builtin_fma(-r2, y2, 1.0);
     const double g = gm * (y2 * y);
