@@ -10,24 +10,18 @@
 //   (M^T u)_q = -G sum_{j != q} u_j . d_qj / |d_qj|^3,
 // one all-pairs pass over (r, m, u) with the same tiling as the force pass.
 #include "common.hpp"
+#include "pair_math.hpp"
 
 namespace nb {
 namespace {
+
+using namespace pm;
 
 struct __attribute__((aligned(64))) ASrc {
     double x, y, z, m, ux, uy, uz, pad;
 };
 
 constexpr double kPad = 1.0e18;
-
-// 1/r to full FP64 accuracy (see the force pass): y0 from the FP32 reciprocal
-// square root, e = 1 - r2 y0^2, 1/r = y0 (1 + e/2 + 3/8 e^2 + O(e^3)).
-__device__ __forceinline__ double rinv_f64(double r2)
-{
-    const double y = (double)__builtin_amdgcn_rsqf((float)r2);
-    const double e = __builtin_fma(-r2, y * y, 1.0);
-    return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
-}
 
 // Sources [0, cnt) of the LDS tile (cnt is the same for the whole workgroup).
 template <int T, int W, bool MASK>

@@ -2,9 +2,12 @@
 // realises Eqs. (3)-(4), the class-order gather/scatter of the split form,
 // and the diagnostics of Sec. 2 (energy, momenta).
 #include "common.hpp"
+#include "pair_math.hpp"
 
 namespace nb {
 namespace {
+
+using namespace pm;
 
 constexpr int kBlock = 256;
 
@@ -170,15 +173,6 @@ __device__ __forceinline__ void cmerge(CSum& a, const CSum& b)
 {
     cadd(a, b.s);
     cadd(a, b.c);
-}
-
-// 1/r to full FP64 accuracy: y0 from the FP32 hardware reciprocal square root,
-// e = 1 - r2 y0^2 (one rounding), 1/r = y0 (1 + e/2 + 3/8 e^2 + O(e^3)).
-__device__ __forceinline__ double rinv_f64(double r2)
-{
-    const double y = (double)__builtin_amdgcn_rsqf((float)r2);
-    const double e = __builtin_fma(-r2, y * y, 1.0);
-    return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
 }
 
 constexpr int kRowTile = 256;

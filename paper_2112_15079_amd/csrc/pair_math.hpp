@@ -50,6 +50,15 @@ static __device__ __forceinline__ double gm_rinv3_newton1(double r2, double gm)
     return gm * (y1 * y1 * y1);
 }
 
+// 1/r to full FP64 accuracy (as gm_rinv3_f64): y0 = v_rsq_f64(r2), e = 1 - r2 y0^2,
+// 1/r = y0 (1 - e)^(-1/2) = y0 (1 + e/2 + 3/8 e^2 + O(e^3)).
+static __device__ __forceinline__ double rinv_f64(double r2)
+{
+    const double y = __builtin_amdgcn_rsq(r2);
+    const double e = __builtin_fma(-r2, y * y, 1.0);
+    return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
+}
+
 // Kahan's compensated addition: s + x with the rounding error carried in c.
 static __device__ __forceinline__ void kahan_add(float& s, float& c, float x)
 {
