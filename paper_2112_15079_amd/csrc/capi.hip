@@ -657,6 +657,7 @@ int32_t nbody_get_tile(int32_t kind, int32_t precision, int64_t n, nbody_tile* t
     g_err.clear();
     if (!tile_host || kind < 0 || kind > 2 || (kind != 2 && n < 1))
         return fail(NBODY_EINVAL, "bad arguments");
+    NB_TRY(check_prec(precision, 0.0));
     if (kind == 2) n = 0;
     const Tile t = pick_tile(kind, precision, n);
     tile_host->targets_per_lane = t.tpl;
@@ -671,11 +672,13 @@ int32_t nbody_set_tile(int32_t kind, int32_t precision, int64_t n, const nbody_t
     g_err.clear();
     if (!tile_host || kind < 0 || kind > 2 || (kind != 2 && n < 1))
         return fail(NBODY_EINVAL, "bad arguments");
+    NB_TRY(check_prec(precision, 0.0));
     if (kind == 2) n = 0;
     Tile t{tile_host->targets_per_lane, tile_host->waves, tile_host->chunks, tile_host->variant};
     if (!tile_supported(t) || (kind == 1 && (t.tpl > 2 || t.waves > 4 || t.variant != 0)) ||
         (t.variant == 3 && (kind != 0 || n > kSmallMax)) || (t.variant == 4 && kind != 0))
-        return fail(NBODY_EINVAL, "unsupported tile (%d, %d, %d)", t.tpl, t.waves, t.chunks);
+        return fail(NBODY_EINVAL, "unsupported tile (%d, %d, %d, variant %d) for kind %d",
+                    t.tpl, t.waves, t.chunks, t.variant, kind);
     std::lock_guard<std::mutex> lk(g_mu);
     g_tiles[std::make_tuple(kind, precision, size_class(n))] = t;
     return NBODY_OK;
@@ -1232,10 +1235,10 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
     std::vector<Tile> cands;
     const int tpls[3] = {1, 2, 4};
     const int waves[4] = {1, 2, 4, 8};
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 4; ++b) {
+    for (int it = 0; it < 3; ++it)
+        for (int iw = 0; iw < 4; ++iw) {
             for (int variant = 0; variant < (kind == 0 ? 3 : 1); ++variant) {
-                Tile t{tpls[a], waves[b], 1, variant};
+                Tile t{tpls[it], waves[iw], 1, variant};
                 if (kind == 1 && (t.tpl > 2 || t.waves > 4)) continue;
                 if (variant != 0 && t.tpl == 4 && t.waves == 8) continue;   // register spills
                 const int64_t tpb = targets_per_block(t);

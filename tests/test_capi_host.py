@@ -144,6 +144,8 @@ def test_tile_table():
     assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(3, 1, 1, 0))) == C.NBODY_EINVAL
     assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(1, 1, 65, 0))) == C.NBODY_EINVAL
     assert lib.nbody_set_tile(1, 0, 100, ctypes.byref(C.Tile(4, 1, 1, 0))) == C.NBODY_EINVAL
+    assert lib.nbody_set_tile(0, 7, 100, ctypes.byref(C.Tile(1, 1, 1, 0))) == C.NBODY_EINVAL
+    assert lib.nbody_get_tile(0, -1, 100, ctypes.byref(t)) == C.NBODY_EINVAL
     lib.nbody_reset_caches()
 
 
