@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU time budget of the oracle sample")
     ap.add_argument("--fd-coords", type=int, default=64, help="adjoint workload: FD coordinates")
+    ap.add_argument("--force-reps", type=int, default=None,
+                    help="launches timed for the force kernel's roofline figure (default: ~0.1 s)")
     ap.add_argument("--tile", default=None,
                     help="fix the FP64 force tile as T,W,C[,variant] (skips autotune)")
     ap.add_argument("--split-tile", default=None, help="fix the split force tile as T,W,C[,variant]")
@@ -188,7 +190,7 @@ def bench_single(args, k, S, nb, torch, np_, dev):
     err64, errsp = acc_err("fp64"), acc_err("split")
 
     # force-kernel timing for the roofline (HIP events around the force kernels only)
-    reps = max(20, min(2000, int(2e11 / pairs)))
+    reps = args.force_reps or max(20, min(2000, int(2e11 / pairs)))
     ms64 = nb.time_force(pos0, m, G, "fp64", reps=reps)
     mssp = nb.time_force(pos0, m, G, "split", reps=reps)
     flops = FLOPS_PER_PAIR * pairs
