@@ -66,6 +66,8 @@ def _load():
     lib.oracle_verlet.restype = ctypes.c_int
     lib.oracle_euler.argtypes = [_I64, _D, _D, _I64, _P, _P, _P]
     lib.oracle_euler.restype = ctypes.c_int
+    lib.oracle_rk4.argtypes = [_I64, _D, _D, _I64, _P, _P, _P]
+    lib.oracle_rk4.restype = ctypes.c_int
     lib.oracle_energy.argtypes = [_I64, _D, _P, _P, _P, _P]
     lib.oracle_momenta.argtypes = [_I64, _P, _P, _P, _P, _P]
     lib.oracle_vjp.argtypes = [_I64, _D, _P, _P, _P, _P, _P]
@@ -169,6 +171,18 @@ def euler(pos, vel, mass, G, dt, steps):
     v = _c(vel, (3, n)).copy()
     if lib.oracle_euler(n, G, dt, int(steps), _ptr(p), _ptr(v), _ptr(mass)) != 0:
         raise MemoryError("oracle_euler allocation failed")
+    return p, v
+
+
+def rk4(pos, vel, mass, G, dt, steps):
+    """Classical fourth-order Runge-Kutta for ``steps`` steps; returns (pos, vel)."""
+    lib = _load()
+    mass = _c(mass)
+    n = mass.shape[0]
+    p = _c(pos, (3, n)).copy()
+    v = _c(vel, (3, n)).copy()
+    if lib.oracle_rk4(n, G, dt, int(steps), _ptr(p), _ptr(v), _ptr(mass)) != 0:
+        raise MemoryError("oracle_rk4 allocation failed")
     return p, v
 
 

@@ -181,6 +181,51 @@ int oracle_euler(int64_t n, double G, double dt, int64_t steps,
     return 0;
 }
 
+/* The classical fourth-order Runge-Kutta method, the higher-order
+ * alternative Sec. 2 names, applied to the first-order system r' = v,
+ * v' = A(r):
+ *   k1 = (v,            A(r))
+ *   k2 = (v + dt/2 kv1, A(r + dt/2 kr1))
+ *   k3 = (v + dt/2 kv2, A(r + dt/2 kr2))
+ *   k4 = (v + dt kv3,   A(r + dt kr3))
+ *   (r, v) += dt/6 (k1 + 2 k2 + 2 k3 + k4).
+ * Four force evaluations per step. */
+int oracle_rk4(int64_t n, double G, double dt, int64_t steps,
+               double* pos, double* vel, const double* mass)
+{
+    int64_t m = 3 * n;
+    double* buf = (double*)malloc(sizeof(double) * m * 10);
+    if (!buf) return -1;
+    double *kr1 = buf, *kv1 = buf + m, *kr2 = buf + 2 * m, *kv2 = buf + 3 * m;
+    double *kr3 = buf + 4 * m, *kv3 = buf + 5 * m, *kr4 = buf + 6 * m, *kv4 = buf + 7 * m;
+    double *rs = buf + 8 * m;   /* the stage position */
+    for (int64_t i = 0; i < steps; ++i) {
+        for (int64_t k = 0; k < m; ++k) kr1[k] = vel[k];
+        oracle_accel(n, G, pos, mass, kv1);
+        for (int64_t k = 0; k < m; ++k) {
+            kr2[k] = vel[k] + 0.5 * dt * kv1[k];
+            rs[k] = pos[k] + 0.5 * dt * kr1[k];
+        }
+        oracle_accel(n, G, rs, mass, kv2);
+        for (int64_t k = 0; k < m; ++k) {
+            kr3[k] = vel[k] + 0.5 * dt * kv2[k];
+            rs[k] = pos[k] + 0.5 * dt * kr2[k];
+        }
+        oracle_accel(n, G, rs, mass, kv3);
+        for (int64_t k = 0; k < m; ++k) {
+            kr4[k] = vel[k] + dt * kv3[k];
+            rs[k] = pos[k] + dt * kr3[k];
+        }
+        oracle_accel(n, G, rs, mass, kv4);
+        for (int64_t k = 0; k < m; ++k) {
+            pos[k] = pos[k] + dt / 6.0 * (kr1[k] + 2.0 * kr2[k] + 2.0 * kr3[k] + kr4[k]);
+            vel[k] = vel[k] + dt / 6.0 * (kv1[k] + 2.0 * kv2[k] + 2.0 * kv3[k] + kv4[k]);
+        }
+    }
+    free(buf);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Diagnostics                                                                */
 /* ------------------------------------------------------------------------ */

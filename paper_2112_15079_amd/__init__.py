@@ -8,13 +8,14 @@ of Eqs. (3)-(4), as hand-written HIP kernels behind the C ABI of
     from paper_2112_15079_amd import accel, verlet_run, verlet_adjoint, \
         verlet_run_batched, energy, momenta, VerletRun
 """
-from .nbody import (SMALL_MASS_MSUN, accel, autotune, autotune_batched, energy, get_flags, get_tile, momenta,
-                    reset_caches, set_tile, time_force, verlet_adjoint, verlet_run, verlet_run_batched,
-                    version)
+from .nbody import (SMALL_MASS_MSUN, accel, autotune, autotune_batched, energy, get_flags, get_tile,
+                    load_tuning, momenta, reset_caches, save_tuning, set_tile, time_force,
+                    verlet_adjoint, verlet_run, verlet_run_batched, version)
 from .autograd import VerletRun, verlet
 
 __all__ = [
     "accel", "verlet_run", "verlet_adjoint", "verlet_run_batched", "energy", "momenta",
-    "get_flags", "get_tile", "set_tile", "autotune", "autotune_batched", "time_force", "reset_caches", "version", "VerletRun",
-    "verlet", "SMALL_MASS_MSUN",
+    "get_flags", "get_tile", "set_tile", "autotune", "autotune_batched", "save_tuning",
+    "load_tuning", "time_force", "reset_caches", "version", "VerletRun", "verlet",
+    "SMALL_MASS_MSUN",
 ]

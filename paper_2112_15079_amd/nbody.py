@@ -8,6 +8,7 @@ marshals arguments; the computation happens in libnbody.so.
 from __future__ import annotations
 
 import ctypes
+import json
 
 import torch
 
@@ -205,6 +206,40 @@ def set_tile(kind, precision, n, targets_per_lane, waves, chunks, variant=0):
             "nbody_set_tile")
 
 
+# Tile shapes chosen by the autotuner in this process, for save_tuning():
+# (kind, precision, n) -> tile dict.
+_tuned = {}
+
+
+def save_tuning(path):
+    """Writes the tile shapes the autotuner chose in this process to a JSON
+    file (device name, library version and one entry per tuned size), which
+    load_tuning() installs in a later process."""
+    entries = [{"kind": k, "precision": p, "n": n, "tile": t} for (k, p, n), t in _tuned.items()]
+    doc = {"library": version(), "device": torch.cuda.get_device_name(), "entries": entries}
+    with open(path, "w") as fh:
+        json.dump(doc, fh, indent=1)
+
+
+def load_tuning(path, strict_device=True):
+    """Installs tile shapes from a save_tuning() file; returns how many.
+    With strict_device, a file written on another device or library version
+    is ignored (returns 0)."""
+    with open(path) as fh:
+        doc = json.load(fh)
+    if strict_device and (doc.get("device") != torch.cuda.get_device_name()
+                          or doc.get("library") != version()):
+        return 0
+    count = 0
+    for e in doc.get("entries", []):
+        t = e["tile"]
+        set_tile(e["kind"], e["precision"], e["n"], t["targets_per_lane"], t["waves"],
+                 t["chunks"], t["variant"])
+        _tuned[(e["kind"], e["precision"], e["n"])] = t
+        count += 1
+    return count
+
+
 def autotune(pos, mass, G, precision="fp64", kind=0, small_mass=None):
     """Times candidate tile shapes on this data, keeps the fastest for n's
     size class; returns (tile dict, ms per pass)."""
@@ -221,6 +256,7 @@ def autotune(pos, mass, G, precision="fp64", kind=0, small_mass=None):
                                  _small(p, small_mass), ws.data_ptr(), ws.numel(),
                                  C.stream_handle(dev), ctypes.byref(t), ctypes.byref(ms))
     C.check(st, "nbody_autotune")
+    _tuned[(int(kind), "fp64" if p == NBODY_FP64 else "split", n)] = t.as_dict()
     return t.as_dict(), float(ms.value)
 
 
@@ -242,6 +278,7 @@ def autotune_batched(pos, mass, offsets, G, precision="fp64", small_mass=None):
                                          _small(p, small_mass), ws.data_ptr(), ws.numel(),
                                          C.stream_handle(dev), ctypes.byref(t), ctypes.byref(ms))
     C.check(st, "nbody_autotune_batched")
+    _tuned[(2, "fp64" if p == NBODY_FP64 else "split", 0)] = t.as_dict()
     return t.as_dict(), float(ms.value)
 
 
@@ -262,7 +299,10 @@ def time_force(pos, mass, G, precision="fp64", kind=0, reps=50, small_mass=None)
 
 
 def reset_caches():
+    """Drops the library's captured graphs, ensemble work lists and tile
+    table (tuned shapes included)."""
     C.load().nbody_reset_caches()
+    _tuned.clear()
 
 
 def version() -> str:

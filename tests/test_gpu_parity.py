@@ -507,6 +507,27 @@ def test_autotune_small_system_then_parity(precision):
     assert rel(H(p), pr) <= (1e-10 if precision == "fp64" else 1e-8)
 
 
+def test_tuning_cache_round_trip(tmp_path):
+    """Autotuned tile shapes saved as JSON and installed in a fresh table."""
+    s = S.config(0)
+    tiles = {prec: nb.autotune(T(s.pos), T(s.mass), s.G, precision=prec)[0]
+             for prec in ("fp64", "split")}
+    path = tmp_path / "tuning.json"
+    nb.save_tuning(path)
+    nb.reset_caches()
+    assert nb.load_tuning(path) == 2
+    for prec, tile in tiles.items():
+        assert nb.get_tile(0, prec, s.n) == tile
+    # a file from another device is ignored unless asked for
+    import json
+    doc = json.loads(path.read_text())
+    doc["device"] = "another device"
+    path.write_text(json.dumps(doc))
+    nb.reset_caches()
+    assert nb.load_tuning(path) == 0
+    assert nb.load_tuning(path, strict_device=False) == 2
+
+
 def test_autotune_then_parity():
     s = S.config(1)
     tile, ms = nb.autotune(T(s.pos), T(s.mass), s.G)

@@ -438,3 +438,66 @@ def test_accel_against_extended_precision():
         worst = max(worst, float(np.linalg.norm(got[:, k] - a.astype(np.float64))
                                  / np.linalg.norm(a.astype(np.float64))))
     assert worst <= 2e-15
+
+
+# ---------------------------------------------------------------------------
+# The classical fourth-order Runge-Kutta method (the higher-order alternative
+# of Sec. 2), pinned to exact two-body solutions.
+
+def test_rk4_circular_orbit_fourth_order():
+    """After one period the circular orbit closes up to an error that falls
+    as dt^4 (halving dt divides it by 16)."""
+    rng = np.random.default_rng(23)
+    G = 2.9591220828e-4
+    errs = []
+    for nstep in (200, 400, 800):
+        pos, vel, mass, w = _circular_pair(1.0, 3e-6, 1.0, G, rng)
+        T = 2 * np.pi / w
+        p, v = oracle.rk4(pos, vel, mass, G, T / nstep, nstep)
+        errs.append(np.linalg.norm((p[:, 1] - p[:, 0]) - (pos[:, 1] - pos[:, 0])))
+    order = np.log2(errs[0] / errs[1]), np.log2(errs[1] / errs[2])
+    # (the next term still shows at these steps: 4.11, then 4.05)
+    assert all(abs(o - 4.0) < 0.15 for o in order), order
+    assert errs[-1] < 1e-8
+
+
+def _kepler_relative(a, e, M, mu):
+    """Relative position and velocity of a Kepler orbit (fixed orientation)."""
+    r, v = S.elements_to_cartesian(np.array([a]), np.array([e]), 0.3, 1.1, 0.7,
+                                   np.array([M]), mu)
+    return r.reshape(3, 1), v.reshape(3, 1)
+
+
+def test_rk4_eccentric_orbit_against_kepler():
+    """An e = 0.5 orbit integrated for 1.3 periods agrees with the Kepler
+    solution (mean anomaly advancing at n = sqrt(mu / a^3)) to O(dt^4)."""
+    G = 2.9591220828e-4
+    m1, m2, a, e = 1.0, 1e-3, 1.5, 0.5
+    mu = G * (m1 + m2)
+    nmean = np.sqrt(mu / a ** 3)
+    t_end = 1.3 * 2 * np.pi / nmean
+    r0, v0 = _kepler_relative(a, e, 0.4, mu)
+    r1, v1 = _kepler_relative(a, e, 0.4 + nmean * t_end, mu)
+    M = m1 + m2
+    pos = np.concatenate([-m2 / M * r0, m1 / M * r0], axis=1)
+    vel = np.concatenate([-m2 / M * v0, m1 / M * v0], axis=1)
+    errs = []
+    for nstep in (1000, 2000, 4000):
+        p, v = oracle.rk4(pos, vel, np.array([m1, m2]), G, t_end / nstep, nstep)
+        errs.append(np.linalg.norm((p[:, 1] - p[:, 0]) - r1[:, 0]) / a)
+    order = np.log2(errs[0] / errs[1]), np.log2(errs[1] / errs[2])
+    assert all(abs(o - 4.0) < 0.2 for o in order), (errs, order)
+    assert errs[-1] < 1e-9
+    # velocity Verlet at the same step is second order: much larger error
+    p2, _ = oracle.verlet(pos, vel, np.array([m1, m2]), G, t_end / 4000, 4000)
+    assert np.linalg.norm((p2[:, 1] - p2[:, 0]) - r1[:, 0]) / a > 100 * errs[-1]
+
+
+def test_rk4_conserves_momentum():
+    """Each stage's accelerations are antisymmetric pair sums, so the total
+    momentum of a random cluster is conserved to roundoff."""
+    pos, vel, mass = S.random_cluster(8, 12, spread=5.0)
+    p, v = oracle.rk4(pos, vel, mass, 0.5, 1e-3, 200)
+    P0 = (mass * vel).sum(axis=1)
+    P1 = (mass * v).sum(axis=1)
+    assert np.linalg.norm(P1 - P0) <= 1e-13 * np.abs(mass * vel).sum()

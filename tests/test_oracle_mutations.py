@@ -47,6 +47,15 @@ MUTATIONS = [
      [P.test_adjoint_dot_product_with_tangent]),
     ("dual-number quotient rule", "(a.d * b.v - a.v * b.d) / (b.v * b.v)",
      "(a.d * b.v + a.v * b.d) / (b.v * b.v)", [P.test_tangent_against_finite_differences]),
+    ("RK4 stage weight", "(kr1[k] + 2.0 * kr2[k] + 2.0 * kr3[k] + kr4[k])",
+     "(kr1[k] + 1.0 * kr2[k] + 2.0 * kr3[k] + kr4[k])",
+     [P.test_rk4_circular_orbit_fourth_order, P.test_rk4_eccentric_orbit_against_kepler]),
+    ("RK4 third-stage position", "rs[k] = pos[k] + 0.5 * dt * kr2[k];",
+     "rs[k] = pos[k] + 0.5 * dt * kr1[k];",
+     [P.test_rk4_circular_orbit_fourth_order, P.test_rk4_eccentric_orbit_against_kepler]),
+    ("RK4 last-stage velocity", "kr4[k] = vel[k] + dt * kv3[k];",
+     "kr4[k] = vel[k] + 0.5 * dt * kv3[k];",
+     [P.test_rk4_circular_orbit_fourth_order, P.test_rk4_eccentric_orbit_against_kepler]),
 ]
 
 
