@@ -70,7 +70,8 @@ typedef enum {
     NBODY_OP_RUN = 1,
     NBODY_OP_ADJOINT = 2,
     NBODY_OP_BATCHED = 3,
-    NBODY_OP_ENERGY = 4
+    NBODY_OP_ENERGY = 4,
+    NBODY_OP_RK4 = 5
 } nbody_op;
 
 /* Bytes of workspace that `op` needs.  n_total: bodies (for BATCHED, the sum
@@ -100,6 +101,20 @@ int32_t nbody_verlet_run(double* pos, double* vel, const double* mass,
                          int64_t n, double G, double dt, int64_t steps,
                          int32_t precision, double small_mass,
                          void* workspace, size_t workspace_bytes, void* stream);
+
+/* The classical fourth-order Runge-Kutta method, the higher-order
+ * alternative to velocity Verlet that Sec. 2 names, for r' = v, v' = a(r)
+ * with a from Eq. (1): advance (pos, vel) in place by `steps` steps of size
+ * dt, four evaluations of Eq. (1) per step (at r, and at the three stage
+ * positions r + dt/2 kr1, r + dt/2 kr2, r + dt kr3); (r, v) += dt/6 (k1 +
+ * 2 k2 + 2 k3 + k4).  Not symplectic: its energy error grows with time,
+ * as O(dt^4).  Arguments, precision, workspace (op NBODY_OP_RK4) and the
+ * non-finite flag as for nbody_verlet_run; steps = 0 is a no-op and runs
+ * chain bit for bit. */
+int32_t nbody_rk4_run(double* pos, double* vel, const double* mass,
+                      int64_t n, double G, double dt, int64_t steps,
+                      int32_t precision, double small_mass,
+                      void* workspace, size_t workspace_bytes, void* stream);
 
 /* Gradient of a scalar loss L(r_T, v_T) of the FP64 run of Eqs. (3)-(4)
  * started from (pos0, vel0) with masses `mass`: the exact discrete adjoint

@@ -18,10 +18,11 @@ LIB_PATH = os.path.join(_HERE, "libnbody.so")
 
 NBODY_OK, NBODY_EINVAL, NBODY_EUNSUPPORTED, NBODY_EWORKSPACE, NBODY_EHIP = range(5)
 NBODY_FP64, NBODY_SPLIT = 0, 1
-OP_ACCEL, OP_RUN, OP_ADJOINT, OP_BATCHED, OP_ENERGY = range(5)
+OP_ACCEL, OP_RUN, OP_ADJOINT, OP_BATCHED, OP_ENERGY, OP_RK4 = range(6)
 
 EXPORTS = (
-    "nbody_workspace_bytes", "nbody_accel", "nbody_verlet_run", "nbody_verlet_adjoint",
+    "nbody_workspace_bytes", "nbody_accel", "nbody_verlet_run", "nbody_rk4_run",
+    "nbody_verlet_adjoint",
     "nbody_verlet_run_batched", "nbody_energy", "nbody_momenta", "nbody_get_flags",
     "nbody_get_tile", "nbody_set_tile", "nbody_autotune", "nbody_autotune_batched",
     "nbody_time_force", "nbody_reset_caches",
@@ -69,6 +70,8 @@ def load():
         lib.nbody_accel.argtypes = [_P, _P, _P, _I64, _D, _D, _I64, _P, _I32, _D, _P, _SZ, _P]
         lib.nbody_verlet_run.restype = _I32
         lib.nbody_verlet_run.argtypes = [_P, _P, _P, _I64, _D, _D, _I64, _I32, _D, _P, _SZ, _P]
+        lib.nbody_rk4_run.restype = _I32
+        lib.nbody_rk4_run.argtypes = [_P, _P, _P, _I64, _D, _D, _I64, _I32, _D, _P, _SZ, _P]
         lib.nbody_verlet_adjoint.restype = _I32
         lib.nbody_verlet_adjoint.argtypes = [_P, _P, _P, _I64, _D, _D, _I64, _I64, _P, _P, _P,
                                              _P, _P, _P, _P, _P, _SZ, _P]

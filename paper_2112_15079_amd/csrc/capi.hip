@@ -88,12 +88,31 @@ constexpr int64_t kFusedMax = 16384;
 // sharing each 64 targets; otherwise about 8192 wavefronts in flight;
 // scalar-operand sources for FP64 below ~3e4 bodies, LDS tiles with 4
 // targets per lane above; the split form prefers the LDS tiles at every size.
+// The force pass alone (variants 0-2): partials for a separate epilogue.
+Tile force_only_tile(int prec, int64_t n)
+{
+    Tile t{1, 1, 1, 0};
+    if (prec == NBODY_FP64) {
+        if (n < 32768) t = Tile{1, n < 4096 ? 1 : 2, 1, 1};
+        else           t = Tile{4, 1, 1, 0};
+    } else if (n >= 32768) {
+        t = Tile{2, 8, 1, 0};
+    }
+    const int64_t tpb = targets_per_block(t);
+    const int64_t tb = (n + tpb - 1) / tpb;
+    int64_t c = std::max<int64_t>(1, 8192 / (tb * t.waves));
+    c = std::min<int64_t>(c, std::max<int64_t>(1, n / (64 * t.waves)));
+    t.chunks = (int)std::min<int64_t>(c, chunk_cap(n));
+    return t;
+}
+
 Tile heuristic_tile(int kind, int prec, int64_t n)
 {
     if (kind == 2) return Tile{2, 1, kBatchChunkMax, 0};   // ensemble: per-system chunks
     if (kind == 0 && n <= kSmallDefault)
         return Tile{1, 16, (int)std::max<int64_t>(1, std::min<int64_t>(16, 1024 / n)), 3};
     if (kind == 0 && n <= kFusedDefault) return Tile{1, 8, 1, 4};
+    if (kind == 0) return force_only_tile(prec, n);
     if (kind == 1) {
         // transpose-Jacobian pass: one wave per 64 targets, sources split in
         // chunks of >= 16 until about 4096 waves are in flight
@@ -103,19 +122,7 @@ Tile heuristic_tile(int kind, int prec, int64_t n)
                                              (int64_t)chunk_cap(n)});
         return Tile{1, 1, (int)c, 0};
     }
-    Tile t{1, 1, 1, 0};
-    if (kind == 0 && prec == NBODY_FP64) {
-        if (n < 32768) t = Tile{1, n < 4096 ? 1 : 2, 1, 1};
-        else           t = Tile{4, 1, 1, 0};
-    } else if (kind == 0) {
-        if (n >= 32768) t = Tile{2, 8, 1, 0};
-    }
-    const int64_t tpb = targets_per_block(t);
-    const int64_t tb = (n + tpb - 1) / tpb;
-    int64_t c = std::max<int64_t>(1, 8192 / (tb * t.waves));
-    c = std::min<int64_t>(c, std::max<int64_t>(1, n / (64 * t.waves)));
-    t.chunks = (int)std::min<int64_t>(c, chunk_cap(n));
-    return t;
+    return Tile{1, 1, 1, 0};
 }
 
 Tile pick_tile(int kind, int prec, int64_t n)
@@ -138,7 +145,7 @@ Tile pick_tile(int kind, int prec, int64_t n)
 struct Layout {
     size_t flags = 0, part = 0, alt = 0, gm = 0, perm = 0, nmaj = 0, offs = 0, pos_c = 0, vel_c = 0,
            mass_c = 0, alt_c = 0, rows = 0, units = 0, bchunks = 0, ck = 0, seg = 0, lam_r = 0,
-           lam_v = 0, g_m = 0, u = 0, vtmp = 0, total = 0;
+           lam_v = 0, g_m = 0, u = 0, vtmp = 0, rk_vs = 0, rk_sr = 0, rk_sv = 0, total = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -174,6 +181,11 @@ Layout layout(int op, int64_t n, int32_t ns, int64_t steps, int64_t K, int prec)
         L.alt_c = a.take(3 * n * d);
     }
     if (op == NBODY_OP_ENERGY) L.rows = a.take(n * d);
+    if (op == NBODY_OP_RK4) {   // stage velocity and slope sums (alt is the stage position)
+        L.rk_vs = a.take(3 * n * d);
+        L.rk_sr = a.take(3 * n * d);
+        L.rk_sv = a.take(3 * n * d);
+    }
     if (op == NBODY_OP_BATCHED) {
         if (!L.offs) L.offs = a.take((size_t)(ns + 1) * sizeof(int64_t));
         // units: per system ceil(n_k/64) target blocks (the smallest tile) times
@@ -450,6 +462,40 @@ int split_prepare(void* ws, const Layout& L, const double* mass, int64_t n, doub
     return NBODY_OK;
 }
 
+// Fourth-order Runge-Kutta: `steps` steps of four force passes and stage
+// updates; the position buffer r is updated in place.  Groups of kRk4Graph
+// steps are replayed from a captured graph.
+constexpr int64_t kRk4Graph = 16;
+
+int rk4_steps(const StepPlan& P, double* r, double* v, double* rs, double* vs, double* sr,
+              double* sv, int64_t steps, hipStream_t stream)
+{
+    auto one = [&](hipStream_t cs) -> int {
+        for (int stage = 1; stage <= 4; ++stage) {
+            NB_TRY(force(P, stage == 1 ? r : rs, cs));
+            NB_HIP(launch_rk4_stage(P.part, P.chunks, P.n, stage, P.dt, r, v, rs, vs, sr, sv,
+                                    P.flags, cs));
+        }
+        return NBODY_OK;
+    };
+    int64_t i = 0;
+    if (steps >= 2 * kRk4Graph) {
+        GraphKey key;
+        key.v = {5, (uint64_t)P.prec, (uint64_t)P.tile.tpl, (uint64_t)P.tile.waves,
+                 (uint64_t)P.tile.chunks, (uint64_t)P.tile.variant, (uint64_t)P.chunks,
+                 (uint64_t)P.n, bits(P.G), bits(P.dt), ptrbits(P.mass), ptrbits(P.gm),
+                 ptrbits(P.part), ptrbits(P.flags), ptrbits(P.nmaj), ptrbits(r), ptrbits(v),
+                 ptrbits(rs), ptrbits(vs), ptrbits(sr), ptrbits(sv)};
+        for (; i + kRk4Graph <= steps; i += kRk4Graph)
+            NB_TRY(run_graph(key, stream, [&](hipStream_t cs) -> int {
+                for (int64_t k = 0; k < kRk4Graph; ++k) NB_TRY(one(cs));
+                return NBODY_OK;
+            }));
+    }
+    for (; i < steps; ++i) NB_TRY(one(stream));
+    return NBODY_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -465,7 +511,7 @@ size_t nbody_workspace_bytes(int32_t op, int64_t n_total, int32_t num_systems, i
                              int64_t checkpoint_every, int32_t precision)
 {
     if (n_total < 1 || n_total > kMaxBodies || num_systems < 1) return 0;
-    if (op < NBODY_OP_ACCEL || op > NBODY_OP_ENERGY) return 0;
+    if (op < NBODY_OP_ACCEL || op > NBODY_OP_RK4) return 0;
     if (precision != NBODY_FP64 && precision != NBODY_SPLIT) return 0;
     if (op == NBODY_OP_ADJOINT && (checkpoint_every < 1 || steps < 0)) return 0;
     return layout(op, n_total, num_systems, steps, checkpoint_every, precision).total;
@@ -607,6 +653,59 @@ int32_t nbody_verlet_run(double* pos, double* vel, const double* mass, int64_t n
     P.buf[1] = alt_c;
     NB_TRY(run_steps(P, steps, s, true));
     NB_HIP(launch_scatter(perm, n, P.buf[steps & 1], pos, 3, s));
+    NB_HIP(launch_scatter(perm, n, vel_c, vel, 3, s));
+    return NBODY_OK;
+}
+
+int32_t nbody_rk4_run(double* pos, double* vel, const double* mass, int64_t n, double G,
+                      double dt, int64_t steps, int32_t precision, double small_mass,
+                      void* workspace, size_t workspace_bytes, void* stream)
+{
+    g_err.clear();
+    NB_TRY(check_common(pos, mass, n, G));
+    NB_TRY(check_prec(precision, small_mass));
+    if (!vel) return fail(NBODY_EINVAL, "vel is NULL");
+    if (steps < 0) return fail(NBODY_EINVAL, "steps must be >= 0");
+    if (!std::isfinite(dt)) return fail(NBODY_EINVAL, "dt is not finite");
+    const Layout L = layout(NBODY_OP_RK4, n, 1, steps, 1, precision);
+    NB_TRY(check_ws(workspace, workspace_bytes, L.total));
+    if (steps == 0) return NBODY_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    StepPlan P;
+    P.prec = precision;
+    P.tile = pick_tile(0, precision, n);
+    if (P.tile.variant >= 3) P.tile = force_only_tile(precision, n);   // whole-step variants
+    P.chunks = effective_chunks(n, P.tile);
+    P.n = n;
+    P.G = G;
+    P.dt = dt;
+    P.part = at<double>(workspace, L.part);
+    P.flags = at<uint32_t>(workspace, L.flags);
+    double* gm = at<double>(workspace, L.gm);
+    P.gm = gm;
+    double* rs = at<double>(workspace, L.alt);
+    double* vs = at<double>(workspace, L.rk_vs);
+    double* sr = at<double>(workspace, L.rk_sr);
+    double* sv = at<double>(workspace, L.rk_sv);
+    if (precision == NBODY_FP64) {
+        P.mass = mass;
+        NB_HIP(launch_scale(mass, G, n, gm, s));
+        return rk4_steps(P, pos, vel, rs, vs, sr, sv, steps, s);
+    }
+    NB_TRY(split_prepare(workspace, L, mass, n, small_mass, s));
+    const int32_t* perm = at<int32_t>(workspace, L.perm);
+    double* pos_c = at<double>(workspace, L.pos_c);
+    double* vel_c = at<double>(workspace, L.vel_c);
+    double* mass_c = at<double>(workspace, L.mass_c);
+    NB_HIP(launch_gather(perm, n, pos, pos_c, 3, s));
+    NB_HIP(launch_gather(perm, n, vel, vel_c, 3, s));
+    NB_HIP(launch_gather(perm, n, mass, mass_c, 1, s));
+    NB_HIP(launch_scale(mass_c, G, n, gm, s));
+    P.mass = mass_c;
+    P.nmaj = at<int64_t>(workspace, L.nmaj);
+    NB_TRY(rk4_steps(P, pos_c, vel_c, rs, vs, sr, sv, steps, s));
+    NB_HIP(launch_scatter(perm, n, pos_c, pos, 3, s));
     NB_HIP(launch_scatter(perm, n, vel_c, vel, 3, s));
     return NBODY_OK;
 }

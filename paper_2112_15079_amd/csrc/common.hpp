@@ -110,6 +110,15 @@ hipError_t launch_step(const double* part, int chunks, const int8_t* body_chunks
                        double* vel, const double* pos_in, double* pos_out, double* acc,
                        double dt, int mode, uint32_t* flags, hipStream_t s);
 
+// ----- fourth-order Runge-Kutta (the alternative integrator of Sec. 2) ---------
+// Stage s = 1..4 after the force pass at the stage position (pos for s = 1,
+// rs otherwise): sums the chunk partials, accumulates the slopes in sr, sv
+// and writes the next stage's position / velocity into rs, vs, or, for
+// s = 4, the step's result into pos, vel.
+hipError_t launch_rk4_stage(const double* part, int chunks, int64_t n, int stage, double dt,
+                            double* pos, double* vel, double* rs, double* vs, double* sr,
+                            double* sv, uint32_t* flags, hipStream_t s);
+
 // ----- split form: class order -------------------------------------------------
 // Stable partition of each system's bodies into mass >= threshold first:
 // perm[body0 + i] = original index of the i-th body in class order, and

@@ -82,6 +82,83 @@ __global__ __launch_bounds__(kBlock) void k_step(const double* __restrict__ part
     if (!finite && flags) atomicOr(flags, 1u);
 }
 
+// Classical fourth-order Runge-Kutta (r' = v, v' = a(r)): stage s's
+// acceleration a (the chunk partials of the force pass at the stage position,
+// summed in ascending chunk order) and the stage velocity give the slopes
+// (kr, kv); sr, sv accumulate kr1 + 2 kr2 + 2 kr3 and kv1 + 2 kv2 + 2 kv3;
+//   s = 1: kr = v,  next stage at (r + dt/2 kr, v + dt/2 kv)
+//   s = 2: kr = vs, next stage at (r + dt/2 kr, v + dt/2 kv)
+//   s = 3: kr = vs, next stage at (r + dt kr,   v + dt kv)
+//   s = 4: kr = vs, r += dt/6 (sr + kr), v += dt/6 (sv + kv).
+template <int GS>
+__global__ __launch_bounds__(kBlock) void k_rk4_stage(const double* __restrict__ part, int chunks,
+                                                      int64_t n, int stage, double dt,
+                                                      double* __restrict__ pos,
+                                                      double* __restrict__ vel,
+                                                      double* __restrict__ rs,
+                                                      double* __restrict__ vs,
+                                                      double* __restrict__ sr,
+                                                      double* __restrict__ sv,
+                                                      uint32_t* __restrict__ flags)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i = t / GS;
+    const int sub = (int)(t % GS);
+    const bool live = i < 3 * n;
+    const int64_t ii = live ? i : 0;
+    const int64_t stride = 3 * n;
+    double a = 0.0;
+    if (live) {
+        for (int c0 = sub; c0 < chunks; c0 += GS * kLoadBatch) {
+            double v[kLoadBatch];
+#pragma unroll
+            for (int u = 0; u < kLoadBatch; ++u) {
+                const int c = c0 + u * GS;
+                v[u] = (c < chunks) ? part[(int64_t)c * stride + ii] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kLoadBatch; ++u)
+                if (c0 + u * GS < chunks) a += v[u];
+        }
+    }
+    if (GS > 1) {
+        double total = a;
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int g = 1; g < GS; ++g) {
+            const double o = __shfl(a, lane + g, 64);
+            if (sub == 0) total += o;
+        }
+        a = total;
+    }
+    if (!live || sub != 0) return;
+    bool finite = __builtin_isfinite(a);
+    const double kr = (stage == 1) ? vel[i] : vs[i];
+    if (stage < 4) {
+        if (stage == 1) {
+            sr[i] = kr;
+            sv[i] = a;
+        } else {
+            sr[i] = sr[i] + 2.0 * kr;
+            sv[i] = sv[i] + 2.0 * a;
+        }
+        const double h = (stage == 3) ? dt : 0.5 * dt;
+        const double r = pos[i] + h * kr;
+        const double v = vel[i] + h * a;
+        finite = finite && __builtin_isfinite(r) && __builtin_isfinite(v);
+        rs[i] = r;
+        vs[i] = v;
+    } else {
+        const double h6 = dt / 6.0;
+        const double r = pos[i] + h6 * (sr[i] + kr);
+        const double v = vel[i] + h6 * (sv[i] + a);
+        finite = finite && __builtin_isfinite(r) && __builtin_isfinite(v);
+        pos[i] = r;
+        vel[i] = v;
+    }
+    if (!finite && flags) atomicOr(flags, 1u);
+}
+
 __global__ __launch_bounds__(kBlock) void k_gather(const int32_t* __restrict__ perm, int64_t n,
                                                    const double* __restrict__ src,
                                                    double* __restrict__ dst, int planes)
@@ -305,6 +382,20 @@ hipError_t launch_step(const double* part, int chunks, const int8_t* body_chunks
         hipLaunchKernelGGL(k_step<1>, dim3(blocks_for(3 * n, kBlock)), dim3(kBlock), 0, s, part,
                            chunks, body_chunks, n, vel, pos_in, pos_out, acc, 0.5 * dt, dt, mode,
                            flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk4_stage(const double* part, int chunks, int64_t n, int stage, double dt,
+                            double* pos, double* vel, double* rs, double* vs, double* sr,
+                            double* sv, uint32_t* flags, hipStream_t s)
+{
+    if (stage < 1 || stage > 4) return hipErrorInvalidValue;
+    if (chunks >= 16)
+        hipLaunchKernelGGL(k_rk4_stage<4>, dim3(blocks_for(12 * n, kBlock)), dim3(kBlock), 0, s,
+                           part, chunks, n, stage, dt, pos, vel, rs, vs, sr, sv, flags);
+    else
+        hipLaunchKernelGGL(k_rk4_stage<1>, dim3(blocks_for(3 * n, kBlock)), dim3(kBlock), 0, s,
+                           part, chunks, n, stage, dt, pos, vel, rs, vs, sr, sv, flags);
     return hipGetLastError();
 }
 

@@ -103,6 +103,25 @@ def verlet_run(pos, vel, mass, G, dt, steps, precision="fp64", small_mass=None):
     return pos, vel
 
 
+def rk4_run(pos, vel, mass, G, dt, steps, precision="fp64", small_mass=None):
+    """Advances (pos, vel) in place by ``steps`` classical fourth-order
+    Runge-Kutta steps (four evaluations of Eq. (1) per step); returns
+    (pos, vel)."""
+    n = _mass(mass)
+    _state(pos, "pos", n)
+    _state(vel, "vel", n)
+    dev = _same_device(pos, vel, mass)
+    p = _prec(precision)
+    steps = int(steps)
+    lib = C.load()
+    ws = C.workspace(C.workspace_bytes(C.OP_RK4, n, steps=steps, precision=p), dev)
+    st = lib.nbody_rk4_run(pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), n, float(G),
+                           float(dt), steps, p, _small(p, small_mass), ws.data_ptr(), ws.numel(),
+                           C.stream_handle(dev))
+    C.check(st, "nbody_rk4_run")
+    return pos, vel
+
+
 def verlet_adjoint(pos0, vel0, mass, G, dt, steps, checkpoint_every, grad_posT, grad_velT):
     """Discrete adjoint of an FP64 run: returns (dL/dr0, dL/dv0, dL/dm, r_T, v_T)
     given dL/dr_T and dL/dv_T."""

@@ -22,7 +22,7 @@ def _lib():
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(nbody_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(nbody_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_the_abi():
@@ -50,6 +50,9 @@ def test_workspace_sizes():
     adj = ws(C.OP_ADJOINT, 2079, 1, 36500, 100, C.NBODY_FP64)
     assert adj >= 366 * 6 * 2079 * 8 + 100 * 3 * 2079 * 8
     assert ws(C.OP_BATCHED, 2_000_000, 512, 1000, 1, C.NBODY_FP64) > 0
+    # RK4: the run's buffers plus stage velocity and two slope sums
+    assert ws(C.OP_RK4, 10425, 1, 5, 1, C.NBODY_FP64) >= ws(C.OP_RUN, 10425, 1, 5, 1, C.NBODY_FP64) \
+        + 3 * 3 * 10425 * 8
     # invalid requests return 0
     assert ws(C.OP_ACCEL, 0, 1, 0, 1, C.NBODY_FP64) == 0
     assert ws(C.OP_ADJOINT, 10, 1, 10, 0, C.NBODY_FP64) == 0
@@ -96,6 +99,18 @@ def test_run_rejects_bad_arguments():
     assert lib.nbody_verlet_run(FAKE, FAKE, FAKE, 5, 1.0, float("inf"), 3, 0, 0.0, ws, big, None) == C.NBODY_EINVAL
     # steps = 0 is a valid no-op (returns before any launch)
     assert lib.nbody_verlet_run(FAKE, FAKE, FAKE, 5, 1.0, 0.1, 0, 0, 0.0, ws, big, None) == C.NBODY_OK
+
+
+def test_rk4_rejects_bad_arguments():
+    lib = _lib()
+    ws = ctypes.c_void_p(0x100000)
+    big = 1 << 40
+    assert lib.nbody_rk4_run(FAKE, None, FAKE, 5, 1.0, 0.1, 3, 0, 0.0, ws, big, None) == C.NBODY_EINVAL
+    assert lib.nbody_rk4_run(FAKE, FAKE, FAKE, 5, 1.0, 0.1, -1, 0, 0.0, ws, big, None) == C.NBODY_EINVAL
+    assert lib.nbody_rk4_run(FAKE, FAKE, FAKE, 5, 1.0, float("nan"), 3, 0, 0.0, ws, big, None) == C.NBODY_EINVAL
+    assert lib.nbody_rk4_run(FAKE, FAKE, FAKE, 5, 1.0, 0.1, 3, 2, 0.0, ws, big, None) == C.NBODY_EINVAL
+    assert lib.nbody_rk4_run(FAKE, FAKE, FAKE, 5, 1.0, 0.1, 3, 0, 0.0, ws, 64, None) == C.NBODY_EWORKSPACE
+    assert lib.nbody_rk4_run(FAKE, FAKE, FAKE, 5, 1.0, 0.1, 0, 0, 0.0, ws, big, None) == C.NBODY_OK
 
 
 def test_adjoint_rejects_bad_arguments():
