@@ -236,9 +236,27 @@ def bench_single(args, k, S, nb, torch, np_, dev):
     }
     if k == 1:
         line["paper_run"] = paper_run(nb, torch, pos0, vel0, m, G, dt)
+        line["rk4"] = rk4_rate(nb, torch, pos0, vel0, m, G, dt, n)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds, k)
     print(json.dumps(line), flush=True)
+
+
+def rk4_rate(nb, torch, pos0, vel0, m, G, dt, n, steps=1000):
+    """Throughput of the fourth-order Runge-Kutta method (four force passes
+    per step) on the same system, FP64, state resident on the GPU."""
+    p, v = pos0.clone(), vel0.clone()
+    nb.rk4_run(p, v, m, G, dt, 64)                          # warm-up on these buffers
+    p.copy_(pos0)
+    v.copy_(vel0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nb.rk4_run(p, v, m, G, dt, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"rk4: {steps} steps in {wall:.4f} s")
+    return {"steps": steps, "steps_per_s": steps / wall,
+            "pairs_per_s": 4 * steps * n * (n - 1) / wall, "force_passes_per_step": 4}
 
 
 PAPER_RUN_S = 23 * 60.0   # Sec. 5: 10^4 bodies, 10^2 days at 0.1 day, 176 CPU processors
@@ -431,9 +449,12 @@ def dt_scan_system(S, n=5000, seed=20, n_moons=100, n_heavy=19):
                           n_major=30, name=f"solar-{n}-dt-scan")
 
 
-def gpu_stepper(nb, torch, dev, s, precision="fp64"):
+def gpu_stepper(nb, torch, dev, s, precision="fp64", integrator="verlet"):
     """advance(dt) -> step(k) running k steps of size dt on the GPU from the
-    system's initial state; step returns (pos, vel, total energy) on the host."""
+    system's initial state (velocity Verlet, or the fourth-order Runge-Kutta
+    method with integrator="rk4"); step returns (pos, vel, total energy) on
+    the host."""
+    run = nb.verlet_run if integrator == "verlet" else nb.rk4_run
     m = torch.tensor(s.mass, dtype=torch.float64, device=dev)
 
     def start(dt):
@@ -441,7 +462,7 @@ def gpu_stepper(nb, torch, dev, s, precision="fp64"):
         v = torch.tensor(s.vel, dtype=torch.float64, device=dev)
 
         def step(k):
-            nb.verlet_run(p, v, m, s.G, dt, k, precision=precision)
+            run(p, v, m, s.G, dt, k, precision=precision)
             return p.cpu().numpy(), v.cpu().numpy(), nb.energy(p, v, m, s.G)[2].item()
         return step
     return start
@@ -518,12 +539,16 @@ def bench_dt_scan(args, S, nb, torch, np_, dev):
     days = 1500.0
     log(f"dt scan: n={s.n}, {days:.0f} days, dt in {dts}, reference dt 0.00625")
     res = dt_scan(gpu_stepper(nb, torch, dev, s), s, dts, days, 10.0, 0.00625)
+    log("the fourth-order Runge-Kutta method, dt in [0.4, 0.2, 0.1, 0.05], reference dt 0.0125")
+    res_rk4 = dt_scan(gpu_stepper(nb, torch, dev, s, integrator="rk4"), s, [0.4, 0.2, 0.1, 0.05],
+                      days, 10.0, 0.0125)
     out = {"metric": "accuracy against the step size", "unit": "relative error",
            "n_gpus": 1, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"{s.name}: Sun, 30 major, 100 moons, 19 heavy, "
                                   f"{s.n - 150} small asteroids; seed 20",
                       "n": s.n, "days": days, "sample_every_days": 10.0}}
     out.update(res)
+    out["rk4"] = res_rk4
     print(json.dumps(out), flush=True)
 
 

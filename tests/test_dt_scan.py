@@ -13,13 +13,15 @@ import oracle
 import solar_ics as S
 
 
-def oracle_stepper(s):
+def oracle_stepper(s, integrator="verlet"):
+    run = oracle.verlet if integrator == "verlet" else oracle.rk4
+
     def start(dt):
         state = [s.pos.copy(), s.vel.copy()]
 
         def step(k):
             if k:
-                state[0], state[1] = oracle.verlet(state[0], state[1], s.mass, s.G, dt, k)
+                state[0], state[1] = run(state[0], state[1], s.mass, s.G, dt, k)
             return state[0], state[1], oracle.energy(state[0], state[1], s.mass, s.G)[2]
         return step
     return start
@@ -52,6 +54,19 @@ def test_dt_scan_oracle_is_second_order():
     assert res["rows"][-1]["dE_over_E_max"] < res["rows"][0]["dE_over_E_max"]
 
 
+def test_dt_scan_oracle_rk4_is_fourth_order():
+    """Positions converge at fourth order; the orbital and total energy errors
+    of these near-Keplerian orbits converge at least as fast (about fifth
+    order here).  Smaller steps would reach roundoff."""
+    s = bench.dt_scan_system(S, **SYSTEM)
+    res = bench.dt_scan(oracle_stepper(s, "rk4"), s, [0.4, 0.2, 0.1], 40.0, 4.0, 0.0125)
+    o = res["orders_log2_ratio"]
+    for key in ("inner_major_pos_err_au", "moon_pos_err_au"):
+        assert all(3.7 <= x <= 4.8 for x in o[key]), (key, o[key])
+    assert all(x >= 3.7 for x in o["inner_major_pos_err_au"] + o["dE_over_E_max"]
+               + o["inner_major_orbit_energy_err"] + o["moon_orbit_energy_err"]), o
+
+
 def test_dt_scan_rejects_a_step_that_does_not_divide_the_sampling():
     s = bench.dt_scan_system(S, **SYSTEM)
     with pytest.raises(ValueError):
@@ -59,12 +74,16 @@ def test_dt_scan_rejects_a_step_that_does_not_divide_the_sampling():
 
 
 @pytest.mark.gpu
-def test_dt_scan_gpu_matches_oracle():
+@pytest.mark.parametrize("integrator", ["verlet", "rk4"])
+def test_dt_scan_gpu_matches_oracle(integrator):
     torch = pytest.importorskip("torch")
     nb = pytest.importorskip("paper_2112_15079_amd")
     s = bench.dt_scan_system(S, **SYSTEM)
-    ref = bench.dt_scan(oracle_stepper(s), s, **SCAN)
-    got = bench.dt_scan(bench.gpu_stepper(nb, torch, "cuda:0", s), s, **SCAN)
+    scan = SCAN if integrator == "verlet" else dict(dts=[0.4, 0.2, 0.1], days=40.0,
+                                                    sample_days=4.0, dt_ref=0.0125)
+    ref = bench.dt_scan(oracle_stepper(s, integrator), s, **scan)
+    got = bench.dt_scan(bench.gpu_stepper(nb, torch, "cuda:0", s, integrator=integrator), s,
+                        **scan)
     assert got["bodies"] == ref["bodies"]
     for a, b in zip(got["rows"], ref["rows"]):
         for key in ("dE_over_E_max", "inner_major_orbit_energy_err", "moon_orbit_energy_err",
