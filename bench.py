@@ -31,6 +31,10 @@ METRIC = "pair interactions/s + steps/s at N=10,425: FP64 vs split-precision at 
 FP64_PEAK_TFLOPS = 78.6          # MI355X vector FP64, 256 CU x 64 lanes x 2 x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 FLOPS_PER_PAIR = 20              # algorithmic convention for one pair interaction
+# each unordered pair once (Newton's third law): the pair's 20 flops serve the
+# target, and the reaction on the source adds 7 (the source-side mass scale
+# and three fused multiply-adds)
+FLOPS_PER_MUTUAL_PAIR = 27
 
 
 def log(msg):
@@ -89,7 +93,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the force pass would "
-              "shard by targets with a per-step all-gather of positions; see DESIGN.md). "
+              "shard by targets with a per-step all-gather of positions). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
@@ -193,11 +197,14 @@ def bench_single(args, k, S, nb, torch, np_, dev):
     reps = args.force_reps or max(20, min(2000, int(2e11 / pairs)))
     ms64 = nb.time_force(pos0, m, G, "fp64", reps=reps)
     mssp = nb.time_force(pos0, m, G, "split", reps=reps)
-    flops = FLOPS_PER_PAIR * pairs
-    achieved = flops / (ms64 * 1e-3) / 1e12
     t64 = tiles["fp64"]
+    mutual = t64["variant"] == 5
+    flops = FLOPS_PER_MUTUAL_PAIR * pairs // 2 if mutual else FLOPS_PER_PAIR * pairs
+    achieved = flops / (ms64 * 1e-3) / 1e12
     kname = ({0: "k_force (LDS tiles)", 1: "k_force_s (scalar operands)",
-              2: "k_force_s (shared targets)", 3: "k_run_small (one workgroup)"}[t64["variant"]]
+              2: "k_force_s (shared targets)", 3: "k_run_small (one workgroup)",
+              4: "k_step_fused (force pass and step)",
+              5: "k_force_mutual (each pair once)"}[t64["variant"]]
              + f" FP64, tile {tile_str(t64)}")
     roof = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3),
             "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -205,6 +212,11 @@ def bench_single(args, k, S, nb, torch, np_, dev):
             "traffic": read_traffic(f"force_fp64_n{n}", t64),
             "ms_per_launch": round(ms64, 5), "flops_per_launch": flops,
             "split_ms_per_launch": round(mssp, 5)}
+    if mutual:
+        # the same launch in the one-way convention (20 flops per ordered pair)
+        eq = FLOPS_PER_PAIR * pairs / (ms64 * 1e-3) / 1e12
+        roof["ordered_pair_equivalent"] = {"achieved": round(eq, 3),
+                                           "frac": round(eq / FP64_PEAK_TFLOPS, 4)}
     log(f"force pass: fp64 {ms64:.4f} ms ({achieved:.2f} TFLOP/s alg.), split {mssp:.4f} ms")
 
     line = {

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libnbody.so")
 SOURCES = ["kernels_force.hip", "kernels_step.hip", "kernels_adjoint.hip", "kernels_small.hip",
-           "capi.hip"]
+           "kernels_mutual.hip", "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -81,13 +81,26 @@ constexpr int64_t kSmallDefault = 160;
 constexpr int64_t kFusedDefault = 512;
 // The autotuner tries the fused force-and-step kernel up to this size.
 constexpr int64_t kFusedMax = 16384;
+// From this size FP64 single systems default to the each-pair-once pass
+// (variant 5, one target block per wave), while its per-range partials fit
+// the workspace (up to 16,384 bodies); below it the pass has too few
+// workgroups to fill the chip.
+constexpr int64_t kMutualDefault = 8500;
+
+// The each-pair-once pass serves single FP64 systems whose per-range
+// partials fit the workspace.
+bool mutual_fits(int kind, int prec, int64_t n)
+{
+    return kind == 0 && prec == NBODY_FP64 && mutual_ranges(n) <= chunk_cap(n);
+}
 
 // Defaults from tile sweeps on MI355X (the autotuner refines them): one
 // workgroup running whole steps for small systems (as many source slices as
 // 1024 lanes allow, at most 16); then one kernel per step with 8 waves
 // sharing each 64 targets; otherwise about 8192 wavefronts in flight;
-// scalar-operand sources for FP64 below ~3e4 bodies, LDS tiles with 4
-// targets per lane above; the split form prefers the LDS tiles at every size.
+// scalar-operand sources for FP64 below ~3e4 bodies (each pair once from
+// 8,500 to 16,384), LDS tiles with 4 targets per lane above; the split form
+// prefers the LDS tiles at every size.
 // The force pass alone (variants 0-2): partials for a separate epilogue.
 Tile force_only_tile(int prec, int64_t n)
 {
@@ -112,6 +125,7 @@ Tile heuristic_tile(int kind, int prec, int64_t n)
     if (kind == 0 && n <= kSmallDefault)
         return Tile{1, 16, (int)std::max<int64_t>(1, std::min<int64_t>(16, 1024 / n)), 3};
     if (kind == 0 && n <= kFusedDefault) return Tile{1, 8, 1, 4};
+    if (n >= kMutualDefault && mutual_fits(kind, prec, n)) return Tile{1, 4, 1, 5};
     if (kind == 0) return force_only_tile(prec, n);
     if (kind == 1) {
         // transpose-Jacobian pass: one wave per 64 targets, sources split in
@@ -130,7 +144,8 @@ Tile pick_tile(int kind, int prec, int64_t n)
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_tiles.find(std::make_tuple(kind, prec, size_class(n)));
-        if (it != g_tiles.end() && !(it->second.variant == 3 && n > kSmallMax)) {
+        if (it != g_tiles.end() && !(it->second.variant == 3 && n > kSmallMax) &&
+            !(it->second.variant == 5 && !mutual_fits(kind, prec, n))) {
             Tile t = it->second;
             t.chunks = std::min(t.chunks, chunk_cap(n));
             return t;
@@ -675,7 +690,8 @@ int32_t nbody_rk4_run(double* pos, double* vel, const double* mass, int64_t n, d
     StepPlan P;
     P.prec = precision;
     P.tile = pick_tile(0, precision, n);
-    if (P.tile.variant >= 3) P.tile = force_only_tile(precision, n);   // whole-step variants
+    if (P.tile.variant == 3 || P.tile.variant == 4)   // whole-step variants
+        P.tile = force_only_tile(precision, n);
     P.chunks = effective_chunks(n, P.tile);
     P.n = n;
     P.G = G;
@@ -775,7 +791,8 @@ int32_t nbody_set_tile(int32_t kind, int32_t precision, int64_t n, const nbody_t
     if (kind == 2) n = 0;
     Tile t{tile_host->targets_per_lane, tile_host->waves, tile_host->chunks, tile_host->variant};
     if (!tile_supported(t) || (kind == 1 && (t.tpl > 2 || t.waves > 4 || t.variant != 0)) ||
-        (t.variant == 3 && (kind != 0 || n > kSmallMax)) || (t.variant == 4 && kind != 0))
+        (t.variant == 3 && (kind != 0 || n > kSmallMax)) || (t.variant == 4 && kind != 0) ||
+        (t.variant == 5 && !mutual_fits(kind, precision, n)))
         return fail(NBODY_EINVAL, "unsupported tile (%d, %d, %d, variant %d) for kind %d",
                     t.tpl, t.waves, t.chunks, t.variant, kind);
     std::lock_guard<std::mutex> lk(g_mu);
@@ -1356,6 +1373,10 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
             }
         }
 
+    if (mutual_fits(kind, precision, n)) {   // each pair once
+        cands.push_back(Tile{1, 4, 1, 5});
+        cands.push_back(Tile{2, 2, 1, 5});
+    }
     if (kind == 0 && n <= kFusedMax) {
         // force pass and step in one kernel, waves of a group splitting the sources
         for (int tpl : {1, 2})
@@ -1388,8 +1409,8 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
                                      kStoreAcc, scratch, nullptr, s));
         } else if (kind == 0) {
             NB_HIP(launch_force(precision, t, pos_w, mass_w, b.gm, n, nmaj, G, part, s));
-            NB_HIP(launch_step(part, effective_chunks(n, t), nullptr, n, nullptr, nullptr, nullptr,
-                               scratch, 0.0, kStoreAcc, nullptr, s));
+            NB_HIP(launch_step(part, effective_chunks(n, t), nullptr, n, nullptr, nullptr,
+                               nullptr, scratch, 0.0, kStoreAcc, nullptr, s));
         } else {
             NB_HIP(launch_vjp(t, pos_w, mass_w, scratch, 1.0, n, G, part, s));
         }

@@ -22,7 +22,10 @@ struct Tile {
                       // 3: one workgroup runs whole steps (n <= kSmallMax, tpl = 1,
                       //    waves = 16, chunks = source slices per target);
                       // 4: as 2 over all sources (chunks = 1) with the step's kicks
-                      //    and drift in the same kernel (tpl 1, 2; waves 2, 4, 8)
+                      //    and drift in the same kernel (tpl 1, 2; waves 2, 4, 8);
+                      // 5: each unordered pair once (FP64; tpl 1 with waves 4, or
+                      //    tpl 2 with waves 2; chunks = 1: the pass writes
+                      //    mutual_ranges(n) partials)
 };
 
 constexpr int kMaxChunks = 64;
@@ -74,6 +77,14 @@ hipError_t launch_force_batched(int precision, const Tile& tile, const double* p
                                 const double* mass, const double* gm, int64_t n_total, double G,
                                 const BatchUnit* units, int64_t num_units, const int64_t* nmaj,
                                 int grid, double* part, hipStream_t s);
+
+// ----- each pair once (variant 5, FP64) -----------------------------------------
+// Ranges of 4 blocks of 64 bodies; the pass writes one partial per range and
+// body (slot order = range order), summed by the ordinary step epilogue.
+int mutual_ranges(int64_t n);
+bool mutual_shape_supported(int tpl, int waves);
+hipError_t launch_force_mutual(int tpl, int waves, const double* pos, const double* gm, int64_t n,
+                               double* part, hipStream_t s);
 
 // ----- small systems: one workgroup, whole steps (variant 3) ----------------
 // Source slices per target actually used for n bodies (0 if n > kSmallMax).

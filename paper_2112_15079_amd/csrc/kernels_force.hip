@@ -570,6 +570,7 @@ __global__ __launch_bounds__(64 * W) void k_force_batched(const double* __restri
 bool tile_supported(const Tile& t)
 {
     if (t.variant == 3) return t.tpl == 1 && t.waves == 16 && t.chunks >= 1 && t.chunks <= kMaxChunks;
+    if (t.variant == 5) return mutual_shape_supported(t.tpl, t.waves) && t.chunks == 1;
     if (t.variant == 4)   // (16 waves of 64 would exceed the register file: spills)
         return (t.tpl == 1 || t.tpl == 2) && (t.waves == 2 || t.waves == 4 || t.waves == 8) &&
                t.chunks == 1;
@@ -661,6 +662,7 @@ static hipError_t launch_batched_tw(int precision, int variant, const double* po
 
 int effective_chunks(int64_t n, const Tile& t)
 {
+    if (t.variant == 5) return mutual_ranges(n);
     const int64_t L = chunk_length(n, t);
     return (int)((n + L - 1) / L);
 }
@@ -669,6 +671,9 @@ hipError_t launch_force(int precision, const Tile& tile, const double* pos, cons
                         const double* gm, int64_t n, const int64_t* nmaj, double G, double* part,
                         hipStream_t s)
 {
+    if (tile.variant == 5)
+        return precision == 0 ? launch_force_mutual(tile.tpl, tile.waves, pos, gm, n, part, s)
+                              : hipErrorInvalidValue;
     if ((tile.variant != 0 && !gm) || tile.variant >= 3) return hipErrorInvalidValue;
     const int64_t L = chunk_length(n, tile);
     const int chunks = effective_chunks(n, tile);

@@ -52,6 +52,9 @@ TILES = [(1, 1, 1, 0), (2, 1, 3, 0), (4, 1, 2, 0), (1, 2, 5, 0), (2, 4, 2, 0), (
          (2, 8, 2, 1), (1, 2, 64, 1), (1, 2, 1, 2), (2, 4, 3, 2), (4, 2, 5, 2), (1, 8, 9, 2)]
 # one workgroup running whole steps (n <= 512): source slices per target
 SMALL_TILES = [(1, 16, 1, 3), (1, 16, 3, 3), (1, 16, 7, 3), (1, 16, 64, 3)]
+# each unordered pair once (FP64): one target block per wave and 4 waves, or
+# two per wave and 2 waves
+MUTUAL = [(1, 4, 1, 5), (2, 2, 1, 5)]
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 131, 257, 1000, 2049])
@@ -59,7 +62,7 @@ def test_accel_fp64_shapes(n):
     s = S.solar_system(50 + n, max(n - 31, 0), n_major=min(30, max(n - 1, 0)))
     pos, mass = s.pos[:, :n], s.mass[:n]
     ref = oracle.accel(pos, mass, s.G)
-    for tile in TILES + (SMALL_TILES if n <= 512 else []):
+    for tile in TILES + (SMALL_TILES if n <= 512 else []) + MUTUAL:
         nb.set_tile(0, "fp64", n, *tile)
         got = H(nb.accel(T(pos), T(mass), s.G))
         e = rel(got, ref)
@@ -267,6 +270,44 @@ def test_fused_step_matches_oracle_and_shared_variant(n, precision):
         assert rel(a, aref) <= atol and rel(p, pr) <= ptol and rel(v, vr) <= 10 * ptol
         for x, y in zip(out[4], out[2]):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("tile", MUTUAL)
+@pytest.mark.parametrize("k", [0, 1])
+def test_mutual_pairs_workloads(k, tile):
+    """Each unordered pair once (Newton's third law) on the two workloads:
+    accelerations against the oracle, a run against the oracle and bitwise
+    repeatable (every partial slot is written once per pass, summed in a
+    fixed order)."""
+    s = S.config(k)
+    nb.set_tile(0, "fp64", s.n, *tile)
+    m = T(s.mass)
+    a = H(nb.accel(T(s.pos), m, s.G))
+    ea = rel(a, oracle.accel(s.pos, s.mass, s.G))
+    steps = 100
+    pr, vr = oracle.verlet(s.pos, s.vel, s.mass, s.G, s.dt, steps)
+    outs = []
+    for _ in range(2):
+        p, v = T(s.pos), T(s.vel)
+        nb.verlet_run(p, v, m, s.G, s.dt, steps)
+        outs.append((H(p), H(v)))
+    ep = rel(outs[0][0], pr)
+    log(f"mutual {tile} workload {k} n={s.n}: accel {ea:.2e}, {steps} steps pos {ep:.2e}")
+    assert ea <= 1e-13 and ep <= 1e-10 and rel(outs[0][1], vr) <= 1e-9
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    # momentum: the pair terms cancel up to the products' rounding
+    P0 = H(nb.momenta(T(s.pos), T(s.vel), m))[:3]
+    P1 = H(nb.momenta(T(outs[0][0]), T(outs[0][1]), m))[:3]
+    assert np.linalg.norm(P1 - P0) <= 1e-12 * np.sum(s.mass * np.linalg.norm(s.vel, axis=0))
+
+
+def test_mutual_pairs_rejected_where_unsupported():
+    s = S.config(2)   # 131,072 bodies need more partial slots than the workspace holds
+    for tile in MUTUAL:
+        with pytest.raises(ValueError):
+            nb.set_tile(0, "fp64", s.n, *tile)
+        with pytest.raises(ValueError):
+            nb.set_tile(0, "split", 1000, *tile)
 
 
 def test_graph_cache_eviction():
