@@ -174,7 +174,16 @@ int32_t nbody_get_flags(void* workspace, void* stream, int32_t clear, int32_t* f
  * Variant 4 (kind 0 only, targets_per_lane 1 or 2, waves 2, 4 or 8, chunks
  * 1): the waves of a workgroup split all sources of its targets, and the
  * same kernel applies the step's kicks and drift, so a step is one launch.
- * The heuristic picks it for 160 < n <= 512. */
+ * The heuristic picks it for 160 < n <= 512.
+ * Variant 5 (kind 0; (targets_per_lane, waves) = (1, 4), (2, 2), (2, 4) or
+ * (4, 4); chunks 1): each unordered pair is evaluated once and the reaction
+ * is added to the source (Newton's third law applied to Eq. (1)); in the
+ * split form pairs of light bodies are evaluated in FP32 both ways and every
+ * pair of a target block holding a heavy body in FP64.  The pass writes one
+ * partial per range of 256 bodies, so it is accepted while
+ * ceil(n / 256) <= 64 (n <= 16,384).  Results stay bitwise repeatable.  The
+ * heuristic picks (4, 4) from n = 4,300 (FP64) or 8,500 (split) up to
+ * n = 16,384. */
 typedef struct {
     int32_t targets_per_lane;
     int32_t waves;

@@ -81,17 +81,20 @@ constexpr int64_t kSmallDefault = 160;
 constexpr int64_t kFusedDefault = 512;
 // The autotuner tries the fused force-and-step kernel up to this size.
 constexpr int64_t kFusedMax = 16384;
-// From this size FP64 single systems default to the each-pair-once pass
-// (variant 5, one target block per wave), while its per-range partials fit
-// the workspace (up to 16,384 bodies); below it the pass has too few
-// workgroups to fill the chip.
-constexpr int64_t kMutualDefault = 8500;
+// From these sizes single systems default to the each-pair-once pass
+// (variant 5, four waves sharing four target blocks per lane), while its
+// per-range partials fit the workspace (up to 16,384 bodies); below them the
+// pass has too few workgroups to fill the chip.  The split form's one-way
+// pass is cheaper than the FP64 one, so its crossover comes later.
+constexpr int64_t kMutualDefault = 4300;
+constexpr int64_t kMutualSplitDefault = 8500;
 
-// The each-pair-once pass serves single FP64 systems whose per-range
-// partials fit the workspace.
+// The each-pair-once pass serves single systems (FP64 or split) whose
+// per-range partials fit the workspace.
 bool mutual_fits(int kind, int prec, int64_t n)
 {
-    return kind == 0 && prec == NBODY_FP64 && mutual_ranges(n) <= chunk_cap(n);
+    (void)prec;
+    return kind == 0 && mutual_ranges(n) <= chunk_cap(n);
 }
 
 // Defaults from tile sweeps on MI355X (the autotuner refines them): one
@@ -99,7 +102,7 @@ bool mutual_fits(int kind, int prec, int64_t n)
 // 1024 lanes allow, at most 16); then one kernel per step with 8 waves
 // sharing each 64 targets; otherwise about 8192 wavefronts in flight;
 // scalar-operand sources for FP64 below ~3e4 bodies (each pair once from
-// 8,500 to 16,384), LDS tiles with 4 targets per lane above; the split form
+// 4,300 to 16,384; split from 8,500), LDS tiles with 4 targets per lane above; the split form
 // prefers the LDS tiles at every size.
 // The force pass alone (variants 0-2): partials for a separate epilogue.
 Tile force_only_tile(int prec, int64_t n)
@@ -125,7 +128,9 @@ Tile heuristic_tile(int kind, int prec, int64_t n)
     if (kind == 0 && n <= kSmallDefault)
         return Tile{1, 16, (int)std::max<int64_t>(1, std::min<int64_t>(16, 1024 / n)), 3};
     if (kind == 0 && n <= kFusedDefault) return Tile{1, 8, 1, 4};
-    if (n >= kMutualDefault && mutual_fits(kind, prec, n)) return Tile{1, 4, 1, 5};
+    if (n >= (prec == NBODY_FP64 ? kMutualDefault : kMutualSplitDefault) &&
+        mutual_fits(kind, prec, n))
+        return Tile{4, 4, 1, 5};
     if (kind == 0) return force_only_tile(prec, n);
     if (kind == 1) {
         // transpose-Jacobian pass: one wave per 64 targets, sources split in
@@ -1373,10 +1378,9 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
             }
         }
 
-    if (mutual_fits(kind, precision, n)) {   // each pair once
-        cands.push_back(Tile{1, 4, 1, 5});
-        cands.push_back(Tile{2, 2, 1, 5});
-    }
+    if (mutual_fits(kind, precision, n))   // each pair once
+        for (const Tile& t : {Tile{1, 4, 1, 5}, Tile{2, 2, 1, 5}, Tile{2, 4, 1, 5}, Tile{4, 4, 1, 5}})
+            cands.push_back(t);
     if (kind == 0 && n <= kFusedMax) {
         // force pass and step in one kernel, waves of a group splitting the sources
         for (int tpl : {1, 2})

@@ -23,8 +23,8 @@ struct Tile {
                       //    waves = 16, chunks = source slices per target);
                       // 4: as 2 over all sources (chunks = 1) with the step's kicks
                       //    and drift in the same kernel (tpl 1, 2; waves 2, 4, 8);
-                      // 5: each unordered pair once (FP64; tpl 1 with waves 4, or
-                      //    tpl 2 with waves 2; chunks = 1: the pass writes
+                      // 5: each unordered pair once ((tpl, waves) = (1, 4),
+                      //    (2, 2), (2, 4), (4, 4); chunks = 1: the pass writes
                       //    mutual_ranges(n) partials)
 };
 
@@ -83,8 +83,9 @@ hipError_t launch_force_batched(int precision, const Tile& tile, const double* p
 // body (slot order = range order), summed by the ordinary step epilogue.
 int mutual_ranges(int64_t n);
 bool mutual_shape_supported(int tpl, int waves);
-hipError_t launch_force_mutual(int tpl, int waves, const double* pos, const double* gm, int64_t n,
-                               double* part, hipStream_t s);
+hipError_t launch_force_mutual(int precision, int tpl, int waves, const double* pos,
+                               const double* gm, int64_t n, const int64_t* nmaj, double* part,
+                               hipStream_t s);
 
 // ----- small systems: one workgroup, whole steps (variant 3) ----------------
 // Source slices per target actually used for n bodies (0 if n > kSmallMax).

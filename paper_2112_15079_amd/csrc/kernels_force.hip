@@ -672,8 +672,7 @@ hipError_t launch_force(int precision, const Tile& tile, const double* pos, cons
                         hipStream_t s)
 {
     if (tile.variant == 5)
-        return precision == 0 ? launch_force_mutual(tile.tpl, tile.waves, pos, gm, n, part, s)
-                              : hipErrorInvalidValue;
+        return launch_force_mutual(precision, tile.tpl, tile.waves, pos, gm, n, nmaj, part, s);
     if ((tile.variant != 0 && !gm) || tile.variant >= 3) return hipErrorInvalidValue;
     const int64_t L = chunk_length(n, tile);
     const int chunks = effective_chunks(n, tile);

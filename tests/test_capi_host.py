@@ -142,14 +142,15 @@ def test_tile_table():
     lib = _lib()
     lib.nbody_reset_caches()
     t = C.Tile()
-    # FP64 defaults: each pair once (variant 5) from 8,500 to 16,384 bodies,
-    # one-way passes on either side; the split form never takes variant 5
-    for n, variant in [(8000, 1), (8500, 5), (10425, 5), (16384, 5), (16385, 1), (40000, 0)]:
-        assert lib.nbody_get_tile(0, 0, n, ctypes.byref(t)) == C.NBODY_OK
-        assert t.variant == variant, (n, t.variant)
-        assert lib.nbody_get_tile(0, 1, n, ctypes.byref(t)) == C.NBODY_OK and t.variant != 5
+    # defaults: each pair once (variant 5) up to 16,384 bodies, from 4,300
+    # (FP64) or 8,500 (split), one-way passes on either side
+    for prec, n, variant in [(0, 4299, 1), (0, 4300, 5), (0, 10425, 5), (0, 16384, 5),
+                             (0, 16385, 1), (0, 40000, 0), (1, 8499, 0), (1, 8500, 5),
+                             (1, 10425, 5), (1, 16384, 5), (1, 16385, 0)]:
+        assert lib.nbody_get_tile(0, prec, n, ctypes.byref(t)) == C.NBODY_OK
+        assert t.variant == variant, (prec, n, t.variant)
     assert lib.nbody_get_tile(0, 0, 10425, ctypes.byref(t)) == C.NBODY_OK
-    assert (t.targets_per_lane, t.waves, t.chunks) == (1, 4, 1)
+    assert (t.targets_per_lane, t.waves, t.chunks) == (4, 4, 1)
     want = C.Tile(4, 2, 7, 0)
     assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(want)) == C.NBODY_OK
     assert lib.nbody_get_tile(0, 0, 10425, ctypes.byref(t)) == C.NBODY_OK
@@ -204,15 +205,16 @@ def test_tile_table_single_workgroup_variant():
     assert lib.nbody_set_tile(1, 0, 3000, ctypes.byref(C.Tile(1, 2, 1, 4))) == C.NBODY_EINVAL
     assert lib.nbody_set_tile(2, 0, 0, ctypes.byref(C.Tile(1, 2, 1, 4))) == C.NBODY_EINVAL
     assert lib.nbody_set_tile(2, 0, 0, ctypes.byref(C.Tile(1, 16, 4, 3))) == C.NBODY_EINVAL
-    # variant 5 (each pair once): FP64 single systems, (1, 4) or (2, 2), one chunk,
+    # variant 5 (each pair once): single systems, (1, 4), (2, 2), (2, 4) or (4, 4), one chunk,
     # while the per-range partials fit the workspace (131,072 bodies: 512 ranges)
-    for good in [(1, 4, 1, 5), (2, 2, 1, 5)]:
+    for good in [(1, 4, 1, 5), (2, 2, 1, 5), (2, 4, 1, 5), (4, 4, 1, 5)]:
         assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(*good))) == C.NBODY_OK, good
         assert lib.nbody_get_tile(0, 0, 10425, ctypes.byref(t)) == C.NBODY_OK
         assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == good
-    for bad in [(2, 4, 4, 5), (1, 4, 2, 5), (2, 4, 1, 5), (1, 2, 1, 5), (4, 1, 1, 5)]:
+    for bad in [(2, 4, 4, 5), (1, 4, 2, 5), (1, 8, 1, 5), (1, 2, 1, 5), (4, 1, 1, 5), (4, 2, 1, 5)]:
         assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(*bad))) == C.NBODY_EINVAL, bad
-    for kind, prec, n in [(0, 1, 10425), (1, 0, 10425), (2, 0, 0), (0, 0, 131072)]:
+    assert lib.nbody_set_tile(0, 1, 10425, ctypes.byref(C.Tile(4, 4, 1, 5))) == C.NBODY_OK
+    for kind, prec, n in [(1, 0, 10425), (2, 0, 0), (0, 0, 131072), (0, 1, 131072)]:
         assert lib.nbody_set_tile(kind, prec, n, ctypes.byref(C.Tile(1, 4, 1, 5))) == C.NBODY_EINVAL
     lib.nbody_reset_caches()
 

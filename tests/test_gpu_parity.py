@@ -52,9 +52,10 @@ TILES = [(1, 1, 1, 0), (2, 1, 3, 0), (4, 1, 2, 0), (1, 2, 5, 0), (2, 4, 2, 0), (
          (2, 8, 2, 1), (1, 2, 64, 1), (1, 2, 1, 2), (2, 4, 3, 2), (4, 2, 5, 2), (1, 8, 9, 2)]
 # one workgroup running whole steps (n <= 512): source slices per target
 SMALL_TILES = [(1, 16, 1, 3), (1, 16, 3, 3), (1, 16, 7, 3), (1, 16, 64, 3)]
-# each unordered pair once (FP64): one target block per wave and 4 waves, or
-# two per wave and 2 waves
-MUTUAL = [(1, 4, 1, 5), (2, 2, 1, 5)]
+# each unordered pair once (FP64): T target blocks per wave, W waves; with
+# T * W = 8 or 16 two or four waves share each target set and split the
+# source blocks
+MUTUAL = [(1, 4, 1, 5), (2, 2, 1, 5), (2, 4, 1, 5), (4, 4, 1, 5)]
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 131, 257, 1000, 2049])
@@ -70,7 +71,7 @@ def test_accel_fp64_shapes(n):
         assert e <= 1e-13
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 5])
 @pytest.mark.parametrize("n", [3, 200, 1031])
 def test_accel_split_shapes(n, variant):
     """Split form on ragged sizes with the class boundary inside a group/tile."""
@@ -78,7 +79,8 @@ def test_accel_split_shapes(n, variant):
         pytest.skip("the single-workgroup variant holds at most 512 bodies")
     s = S.solar_system(70 + n, max(n - 31, 0), n_major=min(30, n - 1))
     ref = oracle.accel(s.pos, s.mass, s.G)
-    shapes = [(1, 16, 1), (1, 16, 2), (1, 16, 5)] if variant == 3 else [(1, 1, 1), (2, 2, 3), (4, 1, 2)]
+    shapes = ([(1, 16, 1), (1, 16, 2), (1, 16, 5)] if variant == 3 else
+              [t[:3] for t in MUTUAL] if variant == 5 else [(1, 1, 1), (2, 2, 3), (4, 1, 2)])
     for tile in shapes:
         nb.set_tile(0, "split", n, *tile, variant)
         got = H(nb.accel(T(s.pos), T(s.mass), s.G, precision="split"))
@@ -218,7 +220,8 @@ def test_single_workgroup_two_elements_per_lane(n, slices, precision):
     assert rel(got, oracle.accel(s.pos, s.mass, s.G)) <= (1e-13 if precision == "fp64" else 2e-12)
 
 
-@pytest.mark.parametrize("tile", [(1, 16, 7, 3), (1, 1, 2, 1), (1, 1, 1, 0)])
+@pytest.mark.parametrize("tile", [(1, 16, 7, 3), (1, 1, 2, 1), (1, 1, 1, 0), (4, 4, 1, 5),
+                                  (1, 4, 1, 5)])
 @pytest.mark.parametrize("threshold,tol_sun,tol", [(0.0, 2e-12, 2e-12), (0.5, 2e-6, 1e-9),
                                                    (2.0, 2e-6, 2e-6)])
 def test_split_class_boundaries(threshold, tol_sun, tol, tile):
@@ -301,13 +304,38 @@ def test_mutual_pairs_workloads(k, tile):
     assert np.linalg.norm(P1 - P0) <= 1e-12 * np.sum(s.mass * np.linalg.norm(s.vel, axis=0))
 
 
+@pytest.mark.parametrize("tile", [(4, 4, 1, 5), (2, 4, 1, 5)])
+@pytest.mark.parametrize("k", [0, 1])
+def test_mutual_pairs_split_workloads(k, tile):
+    """Split form with each pair once: FP32 light-light tiles, FP64 tiles for
+    the heavy bodies' target blocks.  Accelerations within the split bar,
+    energy within 1e-10 of the FP64 run's after 200 steps, bitwise repeat."""
+    s = S.config(k)
+    nb.set_tile(0, "split", s.n, *tile)
+    m = T(s.mass)
+    a = H(nb.accel(T(s.pos), m, s.G, precision="split"))
+    ea = rel(a, oracle.accel(s.pos, s.mass, s.G))
+    steps = 200
+    outs = []
+    for _ in range(2):
+        p, v = T(s.pos), T(s.vel)
+        nb.verlet_run(p, v, m, s.G, s.dt, steps, precision="split")
+        outs.append((p, v))
+    p1, v1 = T(s.pos), T(s.vel)
+    nb.verlet_run(p1, v1, m, s.G, s.dt, steps)
+    E0 = H(nb.energy(T(s.pos), T(s.vel), m, s.G))[2]
+    d = abs(H(nb.energy(*outs[0], m, s.G))[2] - H(nb.energy(p1, v1, m, s.G))[2]) / abs(E0)
+    log(f"mutual split {tile} workload {k} n={s.n}: accel {ea:.2e}, |E_split - E_fp64|/|E0| {d:.2e}")
+    assert ea <= 2e-12 and d <= 1e-10
+    assert np.array_equal(H(outs[0][0]), H(outs[1][0])) and np.array_equal(H(outs[0][1]), H(outs[1][1]))
+
+
 def test_mutual_pairs_rejected_where_unsupported():
     s = S.config(2)   # 131,072 bodies need more partial slots than the workspace holds
     for tile in MUTUAL:
-        with pytest.raises(ValueError):
-            nb.set_tile(0, "fp64", s.n, *tile)
-        with pytest.raises(ValueError):
-            nb.set_tile(0, "split", 1000, *tile)
+        for precision in ("fp64", "split"):
+            with pytest.raises(ValueError):
+                nb.set_tile(0, precision, s.n, *tile)
 
 
 def test_graph_cache_eviction():

@@ -49,7 +49,8 @@ def test_rk4_workload0_matches_oracle(steps):
 
 
 @pytest.mark.parametrize("tile", [None, (1, 1, 1, 0), (2, 4, 3, 0), (1, 2, 7, 1), (1, 4, 2, 2),
-                                  (1, 16, 5, 3), (1, 8, 1, 4), (1, 4, 1, 5), (2, 2, 1, 5)])
+                                  (1, 16, 5, 3), (1, 8, 1, 4), (1, 4, 1, 5), (2, 2, 1, 5),
+                                  (2, 4, 1, 5), (4, 4, 1, 5)])
 @pytest.mark.parametrize("n", [1, 3, 65, 300, 1031])
 def test_rk4_shapes_and_tiles(n, tile):
     """Ragged sizes over the force tiles; whole-step tiles (variants 3, 4)
