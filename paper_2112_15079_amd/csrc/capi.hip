@@ -89,12 +89,22 @@ constexpr int64_t kFusedMax = 16384;
 constexpr int64_t kMutualDefault = 4300;
 constexpr int64_t kMutualSplitDefault = 8500;
 
-// The each-pair-once pass serves single systems (FP64 or split) whose
-// per-range partials fit the workspace.
+// The each-pair-once pass serves single systems (FP64 or split) of up to
+// kMutualMaxN bodies: one partial per range of 256 bodies, 512 slots
+// (1.6 GB of partials) at the largest.
+constexpr int64_t kMutualMaxN = 131072;
+
 bool mutual_fits(int kind, int prec, int64_t n)
 {
     (void)prec;
-    return kind == 0 && mutual_ranges(n) <= chunk_cap(n);
+    return kind == 0 && n <= kMutualMaxN;
+}
+
+// Partial slots of a single system's workspace: the one-way passes' chunks,
+// or one per range where the each-pair-once pass may run.
+int part_slots(int64_t n)
+{
+    return std::max(chunk_cap(n), n <= kMutualMaxN ? mutual_ranges(n) : 0);
 }
 
 // Defaults from tile sweeps on MI355X (the autotuner refines them): one
@@ -186,7 +196,9 @@ Layout layout(int op, int64_t n, int32_t ns, int64_t steps, int64_t K, int prec)
     Alloc a;
     const size_t d = sizeof(double);
     L.flags = a.take(256);
-    const int cap = (op == NBODY_OP_BATCHED) ? kBatchChunkMax : chunk_cap(n);
+    const int cap = op == NBODY_OP_BATCHED ? kBatchChunkMax
+                  : op == NBODY_OP_ENERGY  ? chunk_cap(n)
+                                           : part_slots(n);
     const int planes = (op == NBODY_OP_ADJOINT) ? 4 : 3;
     L.part = a.take((size_t)cap * planes * n * d);
     L.alt = a.take(3 * n * d);

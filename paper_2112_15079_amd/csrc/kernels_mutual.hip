@@ -298,13 +298,17 @@ __global__ __launch_bounds__(64 * KMW) void k_force_mutual(const double* __restr
     __shared__ double racc[kMM][3][64];
     __shared__ double comb[Shape::kShare > 1 ? Shape::kShare - 1 : 1][Shape::kSets][KMT][3][64];
 
-    // blockIdx.x enumerates the pairs (g, r), r >= g, row by row
-    int g = 0, r = (int)blockIdx.x;
-    while (g < ranges - 1 && r >= ranges - g) {
-        r -= ranges - g;
-        ++g;
-    }
-    r += g;
+    // blockIdx.x enumerates the pairs (g, r), r >= g, row by row: row g
+    // starts at S(g) = g*ranges - g(g-1)/2; g from the quadratic's root,
+    // corrected by at most a step either way for rounding
+    const int64_t bid = blockIdx.x;
+    const double R2 = 2.0 * ranges + 1.0;
+    int g = (int)((R2 - __builtin_sqrt(R2 * R2 - 8.0 * (double)bid)) * 0.5);
+    g = g < 0 ? 0 : (g > ranges - 1 ? ranges - 1 : g);
+    auto row_start = [&](int64_t x) { return x * ranges - x * (x - 1) / 2; };
+    if (g > 0 && row_start(g) > bid) --g;
+    if (g < ranges - 1 && row_start(g + 1) <= bid) ++g;
+    const int r = (int)(bid - row_start(g)) + g;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int set = w % Shape::kSets;   // this wave's target set

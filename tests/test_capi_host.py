@@ -50,6 +50,10 @@ def test_workspace_sizes():
     adj = ws(C.OP_ADJOINT, 2079, 1, 36500, 100, C.NBODY_FP64)
     assert adj >= 366 * 6 * 2079 * 8 + 100 * 3 * 2079 * 8
     assert ws(C.OP_BATCHED, 2_000_000, 512, 1000, 1, C.NBODY_FP64) > 0
+    # single systems up to 131,072 bodies hold one partial per 256-body range
+    # for the each-pair-once pass (512 slots at 131,072), beyond that 2^22 / n
+    assert ws(C.OP_RUN, 131072, 1, 5, 1, C.NBODY_FP64) >= 512 * 3 * 131072 * 8
+    assert ws(C.OP_RUN, 131073, 1, 5, 1, C.NBODY_FP64) < 64 * 3 * 131073 * 8
     # RK4: the run's buffers plus stage velocity and two slope sums
     assert ws(C.OP_RK4, 10425, 1, 5, 1, C.NBODY_FP64) >= ws(C.OP_RUN, 10425, 1, 5, 1, C.NBODY_FP64) \
         + 3 * 3 * 10425 * 8
@@ -142,11 +146,11 @@ def test_tile_table():
     lib = _lib()
     lib.nbody_reset_caches()
     t = C.Tile()
-    # defaults: each pair once (variant 5) up to 16,384 bodies, from 4,300
+    # defaults: each pair once (variant 5) up to 131,072 bodies, from 4,300
     # (FP64) or 8,500 (split), one-way passes on either side
-    for prec, n, variant in [(0, 4299, 1), (0, 4300, 5), (0, 10425, 5), (0, 16384, 5),
-                             (0, 16385, 1), (0, 40000, 0), (1, 8499, 0), (1, 8500, 5),
-                             (1, 10425, 5), (1, 16384, 5), (1, 16385, 0)]:
+    for prec, n, variant in [(0, 4299, 1), (0, 4300, 5), (0, 10425, 5), (0, 40000, 5),
+                             (0, 131072, 5), (0, 131073, 0), (1, 8499, 0), (1, 8500, 5),
+                             (1, 10425, 5), (1, 131072, 5), (1, 131073, 0)]:
         assert lib.nbody_get_tile(0, prec, n, ctypes.byref(t)) == C.NBODY_OK
         assert t.variant == variant, (prec, n, t.variant)
     assert lib.nbody_get_tile(0, 0, 10425, ctypes.byref(t)) == C.NBODY_OK
@@ -205,8 +209,8 @@ def test_tile_table_single_workgroup_variant():
     assert lib.nbody_set_tile(1, 0, 3000, ctypes.byref(C.Tile(1, 2, 1, 4))) == C.NBODY_EINVAL
     assert lib.nbody_set_tile(2, 0, 0, ctypes.byref(C.Tile(1, 2, 1, 4))) == C.NBODY_EINVAL
     assert lib.nbody_set_tile(2, 0, 0, ctypes.byref(C.Tile(1, 16, 4, 3))) == C.NBODY_EINVAL
-    # variant 5 (each pair once): single systems, (1, 4), (2, 2), (2, 4) or (4, 4), one chunk,
-    # while the per-range partials fit the workspace (131,072 bodies: 512 ranges)
+    # variant 5 (each pair once): single systems of up to 131,072 bodies (512
+    # ranges of partials), (1, 4), (2, 2), (2, 4) or (4, 4), one chunk
     for good in [(1, 4, 1, 5), (2, 2, 1, 5), (2, 4, 1, 5), (4, 4, 1, 5)]:
         assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(*good))) == C.NBODY_OK, good
         assert lib.nbody_get_tile(0, 0, 10425, ctypes.byref(t)) == C.NBODY_OK
@@ -214,7 +218,7 @@ def test_tile_table_single_workgroup_variant():
     for bad in [(2, 4, 4, 5), (1, 4, 2, 5), (1, 8, 1, 5), (1, 2, 1, 5), (4, 1, 1, 5), (4, 2, 1, 5)]:
         assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(*bad))) == C.NBODY_EINVAL, bad
     assert lib.nbody_set_tile(0, 1, 10425, ctypes.byref(C.Tile(4, 4, 1, 5))) == C.NBODY_OK
-    for kind, prec, n in [(1, 0, 10425), (2, 0, 0), (0, 0, 131072), (0, 1, 131072)]:
+    for kind, prec, n in [(1, 0, 10425), (2, 0, 0), (0, 0, 131073), (0, 1, 131073)]:
         assert lib.nbody_set_tile(kind, prec, n, ctypes.byref(C.Tile(1, 4, 1, 5))) == C.NBODY_EINVAL
     lib.nbody_reset_caches()
 

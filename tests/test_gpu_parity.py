@@ -304,6 +304,29 @@ def test_mutual_pairs_workloads(k, tile):
     assert np.linalg.norm(P1 - P0) <= 1e-12 * np.sum(s.mass * np.linalg.norm(s.vel, axis=0))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_mutual_pairs_more_than_64_ranges(precision):
+    """Each pair once with 79 ranges of partials (more than the one-way
+    passes' 64 chunks): sampled accelerations against the oracle, and 130
+    steps (graph replays) bitwise equal to 65 + 65."""
+    s = S.solar_system(919, 20000 - 150, n_major=30)
+    assert s.n > 64 * 256
+    nb.set_tile(0, precision, s.n, 4, 4, 1, 5)
+    m = T(s.mass)
+    rng = np.random.default_rng(3)
+    idx = np.unique(np.concatenate([[0, 1, 150, s.n - 1], rng.choice(s.n, 60, replace=False)]))
+    got = H(nb.accel(T(s.pos), m, s.G, precision=precision))[:, idx]
+    e = rel(got, oracle.accel_targets(s.pos, s.mass, s.G, idx))
+    log(f"mutual {precision} n={s.n}: sampled accel {e:.2e}")
+    assert e <= (1e-13 if precision == "fp64" else 2e-12)
+    p1, v1 = T(s.pos), T(s.vel)
+    nb.verlet_run(p1, v1, m, s.G, 0.1, 130, precision=precision)
+    p2, v2 = T(s.pos), T(s.vel)
+    nb.verlet_run(p2, v2, m, s.G, 0.1, 65, precision=precision)
+    nb.verlet_run(p2, v2, m, s.G, 0.1, 65, precision=precision)
+    assert np.array_equal(H(p1), H(p2)) and np.array_equal(H(v1), H(v2))
+
+
 @pytest.mark.parametrize("tile", [(4, 4, 1, 5), (2, 4, 1, 5)])
 @pytest.mark.parametrize("k", [0, 1])
 def test_mutual_pairs_split_workloads(k, tile):
@@ -331,11 +354,10 @@ def test_mutual_pairs_split_workloads(k, tile):
 
 
 def test_mutual_pairs_rejected_where_unsupported():
-    s = S.config(2)   # 131,072 bodies need more partial slots than the workspace holds
-    for tile in MUTUAL:
+    for tile in MUTUAL:   # beyond 131,072 bodies (512 ranges of partials)
         for precision in ("fp64", "split"):
             with pytest.raises(ValueError):
-                nb.set_tile(0, precision, s.n, *tile)
+                nb.set_tile(0, precision, 131073, *tile)
 
 
 def test_graph_cache_eviction():
