@@ -180,10 +180,11 @@ int32_t nbody_get_flags(void* workspace, void* stream, int32_t clear, int32_t* f
  * is added to the source (Newton's third law applied to Eq. (1)); in the
  * split form pairs of light bodies are evaluated in FP32 both ways and every
  * pair of a target block holding a heavy body in FP64.  The pass writes one
- * partial per range of 256 bodies, so it is accepted while
- * ceil(n / 256) <= 64 (n <= 16,384).  Results stay bitwise repeatable.  The
- * heuristic picks (4, 4) from n = 4,300 (FP64) or 8,500 (split) up to
- * n = 16,384. */
+ * partial per range of 256 bodies and is accepted for n <= 131,072 (the
+ * workspace of nbody_accel, nbody_verlet_run, nbody_rk4_run and
+ * nbody_verlet_adjoint holds ceil(n / 256) partial slots up to that size:
+ * 1.6 GB at n = 131,072).  Results stay bitwise repeatable.  The heuristic
+ * picks (4, 4) from n = 4,300 (FP64) or 8,500 (split) up to n = 131,072. */
 typedef struct {
     int32_t targets_per_lane;
     int32_t waves;

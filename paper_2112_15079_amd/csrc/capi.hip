@@ -82,9 +82,9 @@ constexpr int64_t kFusedDefault = 512;
 // The autotuner tries the fused force-and-step kernel up to this size.
 constexpr int64_t kFusedMax = 16384;
 // From these sizes single systems default to the each-pair-once pass
-// (variant 5, four waves sharing four target blocks per lane), while its
-// per-range partials fit the workspace (up to 16,384 bodies); below them the
-// pass has too few workgroups to fill the chip.  The split form's one-way
+// (variant 5, four waves sharing four target blocks per lane), up to
+// kMutualMaxN bodies; below them the pass has too few workgroups to fill the
+// chip.  The split form's one-way
 // pass is cheaper than the FP64 one, so its crossover comes later.
 constexpr int64_t kMutualDefault = 4300;
 constexpr int64_t kMutualSplitDefault = 8500;
@@ -112,8 +112,8 @@ int part_slots(int64_t n)
 // 1024 lanes allow, at most 16); then one kernel per step with 8 waves
 // sharing each 64 targets; otherwise about 8192 wavefronts in flight;
 // scalar-operand sources for FP64 below ~3e4 bodies (each pair once from
-// 4,300 to 16,384; split from 8,500), LDS tiles with 4 targets per lane above; the split form
-// prefers the LDS tiles at every size.
+// 4,300, split from 8,500, to 131,072), LDS tiles with 4 targets per lane
+// above; the split form's one-way passes prefer the LDS tiles at every size.
 // The force pass alone (variants 0-2): partials for a separate epilogue.
 Tile force_only_tile(int prec, int64_t n)
 {
