@@ -138,7 +138,11 @@ int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const doubl
  * of different systems do not interact.  offsets_host is a HOST array of
  * num_systems + 1 non-decreasing values starting at 0; every system has at
  * least one body.  The step loop is captured into a HIP graph on first use
- * and replayed. */
+ * and replayed.  Tile: the one nbody_autotune_batched chose, else each pair
+ * once (variant 5, (4, 4)) when every system has at most 10,240 bodies and
+ * sum n_k^2 / sum n_k >= 2,048, else the one-way heuristic; a variant-5 tile
+ * with a system of more than 10,240 bodies gives way to the one-way
+ * heuristic. */
 int32_t nbody_verlet_run_batched(double* pos, double* vel, const double* mass,
                                  const int64_t* offsets_host, int32_t num_systems,
                                  double G, double dt, int64_t steps,
@@ -195,7 +199,9 @@ typedef struct {
 /* The tile shape the library will use for (kind, precision, n): the tuned
  * one if nbody_autotune ran for that size class, else a heuristic.
  * kind: 0 = force pass, 1 = adjoint pass, 2 = batched ensemble (n is
- * ignored; chunks are chosen per system). */
+ * ignored; chunks are chosen per system; without a tuned tile this reports
+ * the one-way heuristic, while a run may take variant 5 from its system
+ * sizes, see nbody_verlet_run_batched). */
 int32_t nbody_get_tile(int32_t kind, int32_t precision, int64_t n, nbody_tile* tile_host);
 
 /* Force a tile shape for (kind, precision, n's size class); shapes outside
@@ -212,8 +218,9 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
                        nbody_tile* best_host, double* best_ms_host);
 
 /* As nbody_autotune for the batched ensemble: times the ensemble's force pass
- * (one launch over all systems' work units) for candidate tile shapes and
- * keeps the fastest for kind 2.  offsets_host as for nbody_verlet_run_batched.
+ * and its epilogue (one launch each over all systems) for candidate tile
+ * shapes, variant 5 among them when every system has at most 10,240 bodies,
+ * and keeps the fastest for kind 2.  offsets_host as for nbody_verlet_run_batched.
  * Synchronises `stream`. */
 int32_t nbody_autotune_batched(int32_t precision, const double* pos, const double* mass,
                                const int64_t* offsets_host, int32_t num_systems, double G,

@@ -60,6 +60,10 @@ std::mutex g_mu;
 std::map<std::tuple<int, int, int>, Tile> g_tiles;   // (kind, precision, size class)
 
 constexpr int kBatchChunkMax = 16;
+// Partial slots of an ensemble's workspace: the one-way passes use at most
+// kBatchChunkMax per body, the each-pair-once pass one per 256-body range of
+// the body's system, so it takes ensembles of systems up to 10,240 bodies.
+constexpr int kBatchSlots = 40;
 
 int size_class(int64_t n)
 {
@@ -97,7 +101,7 @@ constexpr int64_t kMutualMaxN = 131072;
 bool mutual_fits(int kind, int prec, int64_t n)
 {
     (void)prec;
-    return kind == 0 && n <= kMutualMaxN;
+    return (kind == 0 && n <= kMutualMaxN) || kind == 2;   // (ensembles: checked per plan)
 }
 
 // Partial slots of a single system's workspace: the one-way passes' chunks,
@@ -196,7 +200,7 @@ Layout layout(int op, int64_t n, int32_t ns, int64_t steps, int64_t K, int prec)
     Alloc a;
     const size_t d = sizeof(double);
     L.flags = a.take(256);
-    const int cap = op == NBODY_OP_BATCHED ? kBatchChunkMax
+    const int cap = op == NBODY_OP_BATCHED ? kBatchSlots
                   : op == NBODY_OP_ENERGY  ? chunk_cap(n)
                                            : part_slots(n);
     const int planes = (op == NBODY_OP_ADJOINT) ? 4 : 3;
@@ -419,7 +423,10 @@ struct StepPlan {
 
 int force(const StepPlan& P, const double* pos, hipStream_t s)
 {
-    if (P.units)
+    if (P.units && P.tile.variant == 5)
+        NB_HIP(launch_force_mutual_batched(P.prec, P.tile.tpl, P.tile.waves, pos, P.gm, P.n,
+                                           P.units, P.num_units, P.nmaj, P.part, s));
+    else if (P.units)
         NB_HIP(launch_force_batched(P.prec, P.tile, pos, P.mass, P.gm, P.n, P.G, P.units,
                                     P.num_units, P.nmaj, P.grid, P.part, s));
     else
@@ -1022,6 +1029,33 @@ std::shared_ptr<BatchPlan> batch_plan(const int64_t* offs, int32_t ns, const Til
     bp->offsets.assign(offs, offs + ns + 1);
     const int64_t n_total = offs[ns];
     bp->bchunks.resize(n_total);
+    if (t.variant == 5) {
+        // each pair once: units (system, g, r), r >= g, over the system's
+        // ranges, whose count is the system's number of partial slots
+        for (int32_t k = 0; k < ns; ++k) {
+            const int64_t nk = offs[k + 1] - offs[k];
+            const int R = mutual_ranges(nk);
+            if (R > kBatchSlots) {
+                g_batch_used.erase(key);
+                return nullptr;
+            }
+            for (int g = 0; g < R; ++g)
+                for (int r = g; r < R; ++r) {
+                    BatchUnit u;
+                    u.body0 = offs[k];
+                    u.n = (int32_t)nk;
+                    u.sys = k;
+                    u.tblock = g;
+                    u.chunk = r;
+                    u.chunks = R;
+                    u.pad = 0;
+                    bp->units.push_back(u);
+                }
+            std::fill(bp->bchunks.begin() + offs[k], bp->bchunks.begin() + offs[k + 1], (int8_t)R);
+        }
+        g_batch[key] = bp;
+        return bp;
+    }
     const int64_t tb_size = targets_per_block(t);
     for (int32_t k = 0; k < ns; ++k) {
         const int64_t nk = offs[k + 1] - offs[k];
@@ -1074,11 +1108,44 @@ int check_offsets(const int64_t* offsets_host, int32_t num_systems)
     return NBODY_OK;
 }
 
-// Uploads the ensemble's work list for tile t and fills the batched fields of P.
-int batched_plan_upload(const int64_t* offsets_host, int32_t ns, const Tile& t, void* ws,
+// The ensemble's tile: the tuned one if nbody_autotune_batched ran, else
+// each pair once (4, 4) when every system's ranges fit the workspace and the
+// pair-weighted mean system size (sum n^2 / sum n) reaches kBatchMutualMin
+// bodies (smaller systems leave its workgroups mostly idle), else the
+// one-way heuristic.
+constexpr int64_t kBatchMutualMin = 2048;
+
+Tile batch_tile(int prec, const int64_t* offs, int32_t ns)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_tiles.find(std::make_tuple(2, prec, size_class(0)));
+        if (it != g_tiles.end()) return it->second;
+    }
+    double sn = 0.0, sn2 = 0.0;
+    bool fits = true;
+    for (int32_t k = 0; k < ns; ++k) {
+        const double nk = (double)(offs[k + 1] - offs[k]);
+        sn += nk;
+        sn2 += nk * nk;
+        fits = fits && mutual_ranges(offs[k + 1] - offs[k]) <= kBatchSlots;
+    }
+    if (fits && sn2 >= (double)kBatchMutualMin * sn) return Tile{4, 4, 1, 5};
+    return heuristic_tile(2, prec, 0);
+}
+
+// Uploads the ensemble's work list for tile t and fills the batched fields of
+// P.  An each-pair-once tile whose ranges exceed the workspace's slots for
+// some system gives way to the heuristic tile.
+int batched_plan_upload(const int64_t* offsets_host, int32_t ns, const Tile& t_in, void* ws,
                         const Layout& L, hipStream_t s, StepPlan* P)
 {
-    const auto bp = batch_plan(offsets_host, ns, t);
+    Tile t = t_in;
+    auto bp = batch_plan(offsets_host, ns, t);
+    if (!bp) {
+        t = heuristic_tile(2, P->prec, 0);   // one-way, always planned
+        bp = batch_plan(offsets_host, ns, t);
+    }
     const int64_t n = offsets_host[ns];
     BatchUnit* units = at<BatchUnit>(ws, L.units);
     int8_t* bchunks = at<int8_t>(ws, L.bchunks);
@@ -1154,8 +1221,9 @@ int32_t nbody_verlet_run_batched(double* pos, double* vel, const double* mass,
     P.dt = dt;
     P.part = at<double>(workspace, L.part);
     P.flags = at<uint32_t>(workspace, L.flags);
-    NB_TRY(batched_plan_upload(offsets_host, num_systems, pick_tile(2, precision, 0), workspace, L,
-                               s, &P));
+    NB_TRY(batched_plan_upload(offsets_host, num_systems,
+                               batch_tile(precision, offsets_host, num_systems), workspace, L, s,
+                               &P));
     if (precision == NBODY_FP64) {
         double* alt = at<double>(workspace, L.alt);
         double* gm = at<double>(workspace, L.gm);
@@ -1215,6 +1283,19 @@ int32_t nbody_autotune_batched(int32_t precision, const double* pos, const doubl
     for (int tpl : {1, 2, 4})
         for (int w : {1, 2, 4})
             for (int v = 0; v < 3; ++v) cands.push_back(Tile{tpl, w, kBatchChunkMax, v});
+    bool fits = true;   // each pair once, if every system's ranges fit the slots
+    for (int32_t k = 0; k < num_systems; ++k)
+        fits = fits && mutual_ranges(offsets_host[k + 1] - offsets_host[k]) <= kBatchSlots;
+    if (fits)
+        for (const Tile& t : {Tile{2, 4, 1, 5}, Tile{4, 4, 1, 5}}) cands.push_back(t);
+    double* acc_w = at<double>(workspace, L.alt);
+    // a candidate is timed as force pass and epilogue (the partial counts differ)
+    auto pass = [&]() -> int {
+        NB_TRY(force(P, pos_w, s));
+        NB_HIP(launch_step(P.part, 0, P.bchunks, n, nullptr, nullptr, nullptr, acc_w, 0.0,
+                           kStoreAcc, nullptr, s));
+        return NBODY_OK;
+    };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     NB_HIP(hipEventCreate(&e0));
     NB_HIP(hipEventCreate(&e1));
@@ -1225,9 +1306,9 @@ int32_t nbody_autotune_batched(int32_t precision, const double* pos, const doubl
         if ((status = batched_plan_upload(offsets_host, num_systems, t, workspace, L, s, &P)) != NBODY_OK)
             break;
         const int reps = 3;
-        if ((status = force(P, pos_w, s)) != NBODY_OK) break;
+        if ((status = pass()) != NBODY_OK) break;
         if (hipEventRecord(e0, s) != hipSuccess) { status = fail(NBODY_EHIP, "event record"); break; }
-        for (int r = 0; r < reps && status == NBODY_OK; ++r) status = force(P, pos_w, s);
+        for (int r = 0; r < reps && status == NBODY_OK; ++r) status = pass();
         if (status != NBODY_OK) break;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
             status = fail(NBODY_EHIP, "event sync");

@@ -86,6 +86,12 @@ bool mutual_shape_supported(int tpl, int waves);
 hipError_t launch_force_mutual(int precision, int tpl, int waves, const double* pos,
                                const double* gm, int64_t n, const int64_t* nmaj, double* part,
                                hipStream_t s);
+// The ensemble's each-pair-once pass: one workgroup per unit (system,
+// g = tblock, r = chunk, ranges = chunks); partials of stride n_total.
+hipError_t launch_force_mutual_batched(int precision, int tpl, int waves, const double* pos,
+                                       const double* gm, int64_t n_total, const BatchUnit* units,
+                                       int64_t num_units, const int64_t* nmaj, double* part,
+                                       hipStream_t s);
 
 // ----- small systems: one workgroup, whole steps (variant 3) ----------------
 // Source slices per target actually used for n bodies (0 if n > kSmallMax).

@@ -60,14 +60,16 @@ struct Body {
     double x, y, z, gm;
 };
 
+// Body i of a system of n bodies whose coordinate planes are `stride` apart.
 __device__ __forceinline__ Body load_body(const double* __restrict__ pos,
-                                          const double* __restrict__ gm, int64_t n, int64_t i)
+                                          const double* __restrict__ gm, int64_t n,
+                                          int64_t stride, int64_t i)
 {
     Body b;
     if (i < n) {
         b.x = pos[i];
-        b.y = pos[n + i];
-        b.z = pos[2 * n + i];
+        b.y = pos[stride + i];
+        b.z = pos[2 * stride + i];
         b.gm = gm[i];
     } else {
         b.x = kPadBase + kPadStep * (double)i;
@@ -285,12 +287,14 @@ __device__ __forceinline__ void sweep_dispatch32(int d, const double* px, const 
     }
 }
 
+// Workgroup (g, r) of a system of n bodies: pos, gm and part start at the
+// system's first body, coordinate and partial planes are `stride` apart
+// (partial slot c of component k of body i at part[(3c + k) stride + i]).
 template <int KMT, int KMW, bool SPLIT>
-__global__ __launch_bounds__(64 * KMW) void k_force_mutual(const double* __restrict__ pos,
-                                                           const double* __restrict__ gm,
-                                                           int64_t n,
-                                                           const int64_t* __restrict__ nmaj,
-                                                           int ranges, double* __restrict__ part)
+__device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
+                                            const double* __restrict__ gm, int64_t n,
+                                            int64_t stride, int64_t n_major, int g, int r,
+                                            double* __restrict__ part)
 {
     using Shape = MutualShape<KMT, KMW>;
     __shared__ double sx[kMM][128], sy[kMM][128], sz[kMM][128], sg[kMM][128];
@@ -298,17 +302,6 @@ __global__ __launch_bounds__(64 * KMW) void k_force_mutual(const double* __restr
     __shared__ double racc[kMM][3][64];
     __shared__ double comb[Shape::kShare > 1 ? Shape::kShare - 1 : 1][Shape::kSets][KMT][3][64];
 
-    // blockIdx.x enumerates the pairs (g, r), r >= g, row by row: row g
-    // starts at S(g) = g*ranges - g(g-1)/2; g from the quadratic's root,
-    // corrected by at most a step either way for rounding
-    const int64_t bid = blockIdx.x;
-    const double R2 = 2.0 * ranges + 1.0;
-    int g = (int)((R2 - __builtin_sqrt(R2 * R2 - 8.0 * (double)bid)) * 0.5);
-    g = g < 0 ? 0 : (g > ranges - 1 ? ranges - 1 : g);
-    auto row_start = [&](int64_t x) { return x * ranges - x * (x - 1) / 2; };
-    if (g > 0 && row_start(g) > bid) --g;
-    if (g < ranges - 1 && row_start(g + 1) <= bid) ++g;
-    const int r = (int)(bid - row_start(g)) + g;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int set = w % Shape::kSets;   // this wave's target set
@@ -316,14 +309,13 @@ __global__ __launch_bounds__(64 * KMW) void k_force_mutual(const double* __restr
     const int nb = (int)((n + 63) / 64);
     const int I0 = g * kMM + set * KMT;   // this wave's target blocks I0 .. I0 + KMT - 1
     const int J0 = r * kMM;               // the workgroup's source blocks J0 .. J0 + 3
-    const int64_t plane = 3 * n;
-    const int64_t n_major = SPLIT ? nmaj[0] : 0;
+    const int64_t plane = 3 * stride;
 
     Body tg[KMT];
     double ax[KMT], ay[KMT], az[KMT];
 #pragma unroll
     for (int t = 0; t < KMT; ++t) {
-        tg[t] = load_body(pos, gm, n, (int64_t)(I0 + t) * 64 + lane);
+        tg[t] = load_body(pos, gm, n, stride, (int64_t)(I0 + t) * 64 + lane);
         ax[t] = 0.0; ay[t] = 0.0; az[t] = 0.0;
     }
 
@@ -331,7 +323,7 @@ __global__ __launch_bounds__(64 * KMW) void k_force_mutual(const double* __restr
     // of 16, each twice in a row
     for (int jb = w; jb < kMM; jb += KMW) {
         const int64_t j = (int64_t)(J0 + jb) * 64 + lane;
-        const Body b = load_body(pos, gm, n, j);
+        const Body b = load_body(pos, gm, n, stride, j);
         const int a0 = 32 * (lane >> 4) + (lane & 15);
         sx[jb][a0] = b.x; sx[jb][a0 + 16] = b.x;
         sy[jb][a0] = b.y; sy[jb][a0 + 16] = b.y;
@@ -407,8 +399,8 @@ __global__ __launch_bounds__(64 * KMW) void k_force_mutual(const double* __restr
                 if (i < n) {
                     double* pt = part + (int64_t)r * plane;
                     pt[i] = ax[t];
-                    pt[n + i] = ay[t];
-                    pt[2 * n + i] = az[t];
+                    pt[stride + i] = ay[t];
+                    pt[2 * stride + i] = az[t];
                 }
             }
         }
@@ -417,8 +409,8 @@ __global__ __launch_bounds__(64 * KMW) void k_force_mutual(const double* __restr
             if (j < n) {
                 double* ps = part + (int64_t)g * plane;
                 ps[j] = racc[jb][0][lane];
-                ps[n + j] = racc[jb][1][lane];
-                ps[2 * n + j] = racc[jb][2][lane];
+                ps[stride + j] = racc[jb][1][lane];
+                ps[2 * stride + j] = racc[jb][2][lane];
             }
         }
     } else if (h == 0) {
@@ -431,11 +423,45 @@ __global__ __launch_bounds__(64 * KMW) void k_force_mutual(const double* __restr
             if (i < n) {
                 double* pt = part + (int64_t)g * plane;
                 pt[i] = ax[t] + racc[jb][0][lane];
-                pt[n + i] = ay[t] + racc[jb][1][lane];
-                pt[2 * n + i] = az[t] + racc[jb][2][lane];
+                pt[stride + i] = ay[t] + racc[jb][1][lane];
+                pt[2 * stride + i] = az[t] + racc[jb][2][lane];
             }
         }
     }
+}
+
+template <int KMT, int KMW, bool SPLIT>
+__global__ __launch_bounds__(64 * KMW) void k_force_mutual(const double* __restrict__ pos,
+                                                           const double* __restrict__ gm,
+                                                           int64_t n,
+                                                           const int64_t* __restrict__ nmaj,
+                                                           int ranges, double* __restrict__ part)
+{
+    // blockIdx.x enumerates the pairs (g, r), r >= g, row by row: row g
+    // starts at S(g) = g*ranges - g(g-1)/2; g from the quadratic's root,
+    // corrected by at most a step either way for rounding
+    const int64_t bid = blockIdx.x;
+    const double R2 = 2.0 * ranges + 1.0;
+    int g = (int)((R2 - __builtin_sqrt(R2 * R2 - 8.0 * (double)bid)) * 0.5);
+    g = g < 0 ? 0 : (g > ranges - 1 ? ranges - 1 : g);
+    auto row_start = [&](int64_t x) { return x * ranges - x * (x - 1) / 2; };
+    if (g > 0 && row_start(g) > bid) --g;
+    if (g < ranges - 1 && row_start(g + 1) <= bid) ++g;
+    const int r = (int)(bid - row_start(g)) + g;
+    mutual_unit<KMT, KMW, SPLIT>(pos, gm, n, n, SPLIT ? nmaj[0] : 0, g, r, part);
+}
+
+// The ensemble: one workgroup per unit (system, g = tblock, r = chunk) of the
+// work list; the partial planes span all systems (stride n_total).
+template <int KMT, int KMW, bool SPLIT>
+__global__ __launch_bounds__(64 * KMW) void k_force_mutual_batched(
+    const double* __restrict__ pos, const double* __restrict__ gm, int64_t n_total,
+    const BatchUnit* __restrict__ units, const int64_t* __restrict__ nmaj,
+    double* __restrict__ part)
+{
+    const BatchUnit u = units[blockIdx.x];
+    mutual_unit<KMT, KMW, SPLIT>(pos + u.body0, gm + u.body0, u.n, n_total,
+                                 SPLIT ? nmaj[u.sys] : 0, u.tblock, u.chunk, part + u.body0);
 }
 
 }  // namespace
@@ -466,6 +492,44 @@ static void launch_mutual_shape(int tpl, int waves, dim3 grid, const double* pos
     else
         hipLaunchKernelGGL((k_force_mutual<4, 4, SPLIT>), grid, block, 0, s, pos, gm, n, nmaj,
                            ranges, part);
+}
+
+template <bool SPLIT>
+static void launch_mutual_batched_shape(int tpl, int waves, dim3 grid, const double* pos,
+                                        const double* gm, int64_t n_total, const BatchUnit* units,
+                                        const int64_t* nmaj, double* part, hipStream_t s)
+{
+    const dim3 block((unsigned)(64 * waves));
+    if (tpl == 1)
+        hipLaunchKernelGGL((k_force_mutual_batched<1, 4, SPLIT>), grid, block, 0, s, pos, gm,
+                           n_total, units, nmaj, part);
+    else if (tpl == 2 && waves == 2)
+        hipLaunchKernelGGL((k_force_mutual_batched<2, 2, SPLIT>), grid, block, 0, s, pos, gm,
+                           n_total, units, nmaj, part);
+    else if (tpl == 2)
+        hipLaunchKernelGGL((k_force_mutual_batched<2, 4, SPLIT>), grid, block, 0, s, pos, gm,
+                           n_total, units, nmaj, part);
+    else
+        hipLaunchKernelGGL((k_force_mutual_batched<4, 4, SPLIT>), grid, block, 0, s, pos, gm,
+                           n_total, units, nmaj, part);
+}
+
+hipError_t launch_force_mutual_batched(int precision, int tpl, int waves, const double* pos,
+                                       const double* gm, int64_t n_total, const BatchUnit* units,
+                                       int64_t num_units, const int64_t* nmaj, double* part,
+                                       hipStream_t s)
+{
+    if (!gm || !units || num_units < 1 || !mutual_shape_supported(tpl, waves) ||
+        (precision != 0 && !nmaj))
+        return hipErrorInvalidValue;
+    const dim3 grid((unsigned)num_units);
+    if (precision == 0)
+        launch_mutual_batched_shape<false>(tpl, waves, grid, pos, gm, n_total, units, nullptr,
+                                           part, s);
+    else
+        launch_mutual_batched_shape<true>(tpl, waves, grid, pos, gm, n_total, units, nmaj, part,
+                                          s);
+    return hipGetLastError();
 }
 
 hipError_t launch_force_mutual(int precision, int tpl, int waves, const double* pos,

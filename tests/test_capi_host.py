@@ -218,8 +218,13 @@ def test_tile_table_single_workgroup_variant():
     for bad in [(2, 4, 4, 5), (1, 4, 2, 5), (1, 8, 1, 5), (1, 2, 1, 5), (4, 1, 1, 5), (4, 2, 1, 5)]:
         assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(*bad))) == C.NBODY_EINVAL, bad
     assert lib.nbody_set_tile(0, 1, 10425, ctypes.byref(C.Tile(4, 4, 1, 5))) == C.NBODY_OK
-    for kind, prec, n in [(1, 0, 10425), (2, 0, 0), (0, 0, 131073), (0, 1, 131073)]:
+    for kind, prec, n in [(1, 0, 10425), (0, 0, 131073), (0, 1, 131073)]:
         assert lib.nbody_set_tile(kind, prec, n, ctypes.byref(C.Tile(1, 4, 1, 5))) == C.NBODY_EINVAL
+    # ensembles take it too (a plan with a system of more than 40 ranges falls
+    # back to the heuristic tile)
+    for prec in (0, 1):
+        assert lib.nbody_set_tile(2, prec, 0, ctypes.byref(C.Tile(4, 4, 1, 5))) == C.NBODY_OK
+        assert lib.nbody_get_tile(2, prec, 0, ctypes.byref(t)) == C.NBODY_OK and t.variant == 5
     lib.nbody_reset_caches()
 
 

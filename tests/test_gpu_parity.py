@@ -526,6 +526,57 @@ def test_batched_matches_oracle(precision, variant):
         assert e <= tol, (k, x.n, e)
 
 
+def _mixed_ensemble():
+    """Systems of 12 ranges of 256 bodies and of one or two, and a lone Sun."""
+    systems = [S.solar_system(401, 3000, n_major=30), S.solar_system(402, 600, n_major=12),
+               S.solar_system(403, 40, n_major=3), S.solar_system(404, 0, n_major=0)]
+    offs = np.zeros(len(systems) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([x.n for x in systems])
+    cat = lambda f: np.ascontiguousarray(np.concatenate([f(x) for x in systems], axis=-1))
+    return systems, offs, cat(lambda x: x.pos), cat(lambda x: x.vel), cat(lambda x: x.mass)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+@pytest.mark.parametrize("tile", [(4, 4, 1, 5), (2, 4, 1, 5)])
+def test_batched_mutual_matches_oracle(precision, tile):
+    """The ensemble with each pair once: one workgroup per (system, g, r),
+    per-body partial counts equal to the system's ranges; every system
+    against the oracle after 40 steps, and a bitwise repeat."""
+    systems, offs, pos, vel, mass = _mixed_ensemble()
+    nb.set_tile(2, precision, 0, *tile)
+    outs = []
+    for _ in range(2):
+        p, v = T(pos), T(vel)
+        nb.verlet_run_batched(p, v, T(mass), offs, S.G_AU_DAY_MSUN, 0.1, 40, precision=precision)
+        outs.append((H(p), H(v)))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    for k, x in enumerate(systems):
+        a, b = offs[k], offs[k + 1]
+        pr, vr = oracle.verlet(x.pos, x.vel, x.mass, x.G, 0.1, 40)
+        e = rel(outs[0][0][:, a:b], pr)
+        log(f"ensemble mutual {precision} {tile} system {k} (n={x.n}): pos {e:.2e}")
+        assert e <= (1e-12 if precision == "fp64" else 1e-10), (k, x.n, e)
+        assert rel(outs[0][1][:, a:b], vr) <= (1e-11 if precision == "fp64" else 1e-9)
+
+
+def test_batched_mutual_falls_back_beyond_40_ranges():
+    """A system of more than 10,240 bodies (41 ranges) exceeds the ensemble
+    workspace's partial slots: the each-pair-once tile gives way to the
+    heuristic one and the results still match the oracle."""
+    systems = [S.solar_system(405, 10300, n_major=30), S.solar_system(406, 200, n_major=8)]
+    assert systems[0].n > 40 * 256
+    offs = np.zeros(3, dtype=np.int64)
+    offs[1:] = np.cumsum([x.n for x in systems])
+    cat = lambda f: np.ascontiguousarray(np.concatenate([f(x) for x in systems], axis=-1))
+    nb.set_tile(2, "fp64", 0, 4, 4, 1, 5)
+    p, v = T(cat(lambda x: x.pos)), T(cat(lambda x: x.vel))
+    nb.verlet_run_batched(p, v, T(cat(lambda x: x.mass)), offs, S.G_AU_DAY_MSUN, 0.1, 2)
+    P = H(p)
+    for k, x in enumerate(systems):
+        pr, _ = oracle.verlet(x.pos, x.vel, x.mass, x.G, 0.1, 2)
+        assert rel(P[:, offs[k]:offs[k + 1]], pr) <= 1e-12
+
+
 @pytest.mark.parametrize("precision", ["fp64", "split"])
 def test_batched_autotune_then_parity(precision):
     systems, offs, pos, vel, mass = _small_ensemble(count=5)
@@ -541,15 +592,21 @@ def test_batched_autotune_then_parity(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "split"])
-def test_batched_full_ensemble_sampled(precision):
+@pytest.mark.parametrize("how", ["autotune", "mutual", "one-way"])
+def test_batched_full_ensemble_sampled(precision, how):
     """The 512-system ensemble at full size, in the launch configuration the
-    benchmark times (autotuned tile, one batched launch per step), against
-    the oracle on the smallest, the largest and two random member systems."""
+    benchmark times (autotuned tile, one batched launch per step), and with
+    the each-pair-once and the one-way tiles forced, against the oracle on
+    the smallest, the largest and two random member systems."""
     systems, offs = S.ensemble(512)
     cat = lambda f: np.ascontiguousarray(np.concatenate([f(x) for x in systems], axis=-1))
     pos, vel, mass = cat(lambda x: x.pos), cat(lambda x: x.vel), cat(lambda x: x.mass)
     p, v, m = T(pos), T(vel), T(mass)
-    tile, _ = nb.autotune_batched(p, m, offs, S.G_AU_DAY_MSUN, precision)
+    if how == "autotune":
+        tile, _ = nb.autotune_batched(p, m, offs, S.G_AU_DAY_MSUN, precision)
+    else:
+        tile = (4, 4, 1, 5) if how == "mutual" else (4, 1, 16, 0)
+        nb.set_tile(2, precision, 0, *tile)
     steps = 3
     nb.verlet_run_batched(p, v, m, offs, S.G_AU_DAY_MSUN, 0.1, steps, precision=precision)
     P, V = H(p), H(v)
