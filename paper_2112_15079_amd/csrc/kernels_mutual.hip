@@ -11,7 +11,7 @@
 // for how the waves split the (target block, source block) tiles between
 // them.  In phase p wave w works on source block (w + p) mod 4, so in every
 // phase the waves touch different source blocks.
-
+//
 // Within a tile, each row of 16 lanes meets each group of 16 sources in turn
 // (sub-phase q: group (row + q) mod 4) and, within a group, lane c pairs with
 // source (c + k) mod 16 at step k; the reaction sum of that source travels with
@@ -31,14 +31,15 @@
 // FP32 terms both ways; the 16 terms of one sub-phase (a block of 16 sources
 // for a target, of 16 targets for a reaction) are summed in FP32 and each
 // block sum is added to the FP64 accumulators.
-
+//
 // Output: one partial per (body, range) in the chunk layout of the other force
 // passes, so the ordinary step epilogue adds them in slot order.  Workgroup
 // (g, r), r > g, writes its targets' accelerations to slot r and the reactions
 // on its sources to slot g; workgroup (g, g) adds the two for each of its
 // bodies and writes slot g.  A body of range R thus receives slot s < R as a
 // source, slot s > R as a target and slot R from the diagonal workgroup:
-// every slot exactly once.
+// every slot exactly once.  An ensemble runs the same workgroups per system,
+// listed as units (system, g, r), on planes spanning all systems.
 #include "common.hpp"
 #include "pair_math.hpp"
 
@@ -53,8 +54,6 @@ constexpr int kMM = 4;   // blocks per range (source blocks per workgroup, targe
 // they take part in is a finite zero (or goes to a body that is not stored).
 constexpr double kPadBase = 1.0e18;
 constexpr double kPadStep = 1.0e13;
-
-enum TileType { kNone = 0, kDiag = 1, kSym = 2 };
 
 struct Body {
     double x, y, z, gm;
