@@ -1149,6 +1149,11 @@ int batched_plan_upload(const int64_t* offsets_host, int32_t ns, const Tile& t_i
     const int64_t n = offsets_host[ns];
     BatchUnit* units = at<BatchUnit>(ws, L.units);
     int8_t* bchunks = at<int8_t>(ws, L.bchunks);
+    // the unit list's room in the workspace (the layout's bound covers every
+    // plan: per system at most 16 (n_k/64 + 1) units, and each pair once
+    // needs R(R+1)/2 <= 64 (R - 1) + 16 of them for R <= 40 ranges)
+    if (bp->units.size() > (L.bchunks - L.units) / sizeof(BatchUnit))
+        return fail(NBODY_EUNSUPPORTED, "ensemble work list exceeds the workspace");
     NB_HIP(hipMemcpyAsync(units, bp->units.data(), bp->units.size() * sizeof(BatchUnit),
                           hipMemcpyHostToDevice, s));
     NB_HIP(hipMemcpyAsync(bchunks, bp->bchunks.data(), n, hipMemcpyHostToDevice, s));
