@@ -760,7 +760,9 @@ int32_t nbody_energy(const double* pos, const double* vel, const double* mass, i
     NB_TRY(check_ws(workspace, workspace_bytes, L.total));
     hipStream_t s = static_cast<hipStream_t>(stream);
     double* rows = at<double>(workspace, L.rows);
-    NB_HIP(launch_potential_rows(pos, mass, n, G, rows, s));
+    // the partial region holds chunk_cap(n) slots of 3 n doubles for this op
+    NB_HIP(launch_potential_rows(pos, mass, n, G, at<double>(workspace, L.part), chunk_cap(n), rows,
+                                 s));
     NB_HIP(launch_energy_finish(rows, vel, mass, n, out, s));
     return NBODY_OK;
 }

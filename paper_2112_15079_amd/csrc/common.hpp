@@ -151,8 +151,11 @@ hipError_t launch_scatter(const int32_t* perm, int64_t n, const double* src3, do
                           int planes, hipStream_t s);
 
 // ----- diagnostics -------------------------------------------------------------
+// rows[p] = -G m_p / 2 sum_{j != p} m_j / |r_j - r_p| (compensated): source
+// chunks (at most max_chunks; part holds 2 n doubles per chunk) merged in
+// chunk order.
 hipError_t launch_potential_rows(const double* pos, const double* mass, int64_t n, double G,
-                                 double* rows, hipStream_t s);
+                                 double* part, int max_chunks, double* rows, hipStream_t s);
 hipError_t launch_energy_finish(const double* rows, const double* vel, const double* mass,
                                 int64_t n, double* out, hipStream_t s);
 hipError_t launch_momenta(const double* pos, const double* vel, const double* mass, int64_t n,

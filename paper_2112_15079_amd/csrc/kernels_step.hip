@@ -254,38 +254,64 @@ __device__ __forceinline__ void cmerge(CSum& a, const CSum& b)
 
 constexpr int kRowTile = 256;
 
-// rows[p] = -G m_p / 2 * sum_{j != p} m_j / |r_j - r_p|; sum_p rows[p] is the
-// pair potential of Sec. 2 (each pair counted twice, hence the half).
+// Row sums of the pair potential of Sec. 2 over one chunk of sources, each
+// unordered pair once: S_c(p) = sum_{j in chunk c, j > p} m_j / |r_j - r_p|,
+// compensated, stored as (s, c) in part[2c][p], part[2c + 1][p] (grid.y =
+// chunks of chunk_len; a chunk wholly below the row block has nothing to do).
 __global__ __launch_bounds__(kRowTile) void k_potential_rows(const double* __restrict__ pos,
                                                              const double* __restrict__ mass,
-                                                             int64_t n, double G,
-                                                             double* __restrict__ rows)
+                                                             int64_t n, int64_t chunk_len,
+                                                             double* __restrict__ part)
 {
     __shared__ double sx[kRowTile], sy[kRowTile], sz[kRowTile], sm[kRowTile];
     const int tid = threadIdx.x;
     const int64_t p = (int64_t)blockIdx.x * kRowTile + tid;
     const int64_t q = p < n ? p : n - 1;
     const double px = pos[q], py = pos[n + q], pz = pos[2 * n + q];
+    const int64_t je0 = (int64_t)(blockIdx.y + 1) * chunk_len;
+    const int64_t je = je0 < n ? je0 : n;
+    const int64_t row0 = (int64_t)blockIdx.x * kRowTile;
+    // sources j > p only: start at the row block's first row + 1 at the earliest
+    const int64_t jb = (int64_t)blockIdx.y * chunk_len > row0 + 1 ? (int64_t)blockIdx.y * chunk_len
+                                                                  : row0 + 1;
     CSum acc = {0.0, 0.0};
-    for (int64_t j0 = 0; j0 < n; j0 += kRowTile) {
+    for (int64_t j0 = jb; j0 < je; j0 += kRowTile) {
         const int64_t j = j0 + tid;
         __syncthreads();
-        if (j < n) {
+        if (j < je) {
             sx[tid] = pos[j];
             sy[tid] = pos[n + j];
             sz[tid] = pos[2 * n + j];
             sm[tid] = mass[j];
         }
         __syncthreads();
-        const int cnt = (n - j0 < kRowTile) ? (int)(n - j0) : kRowTile;
+        const int cnt = (je - j0 < kRowTile) ? (int)(je - j0) : kRowTile;
         for (int jj = 0; jj < cnt; ++jj) {
-            if (j0 + jj == q) continue;
+            if (j0 + jj <= q) continue;
             const double dx = sx[jj] - px, dy = sy[jj] - py, dz = sz[jj] - pz;
             const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
             cadd(acc, sm[jj] * rinv_f64(r2));
         }
     }
-    if (p < n) rows[p] = -0.5 * G * mass[p] * (acc.s + acc.c);
+    if (p < n) {
+        part[(int64_t)(2 * blockIdx.y) * n + p] = acc.s;
+        part[(int64_t)(2 * blockIdx.y + 1) * n + p] = acc.c;
+    }
+}
+
+// rows[p] = -G m_p * (the chunk sums merged in chunk order); sum_p rows[p] is
+// the pair potential (each unordered pair once).
+__global__ __launch_bounds__(kBlock) void k_potential_merge(const double* __restrict__ part,
+                                                            int chunks, const double* __restrict__ mass,
+                                                            int64_t n, double G,
+                                                            double* __restrict__ rows)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    CSum m = {0.0, 0.0};
+    for (int c = 0; c < chunks; ++c)
+        cmerge(m, CSum{part[(int64_t)(2 * c) * n + p], part[(int64_t)(2 * c + 1) * n + p]});
+    rows[p] = -G * mass[p] * (m.s + m.c);
 }
 
 constexpr int kRed = 1024;
@@ -425,10 +451,20 @@ hipError_t launch_scatter(const int32_t* perm, int64_t n, const double* src, dou
 }
 
 hipError_t launch_potential_rows(const double* pos, const double* mass, int64_t n, double G,
-                                 double* rows, hipStream_t s)
+                                 double* part, int max_chunks, double* rows, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_potential_rows, dim3(blocks_for(n, kRowTile)), dim3(kRowTile), 0, s,
-                       pos, mass, n, G, rows);
+    // source chunks of whole tiles until about 1024 workgroups have work (half
+    // of the (row block, chunk) grid lies below the diagonal)
+    const int64_t row_blocks = blocks_for(n, kRowTile);
+    int64_t c = (2048 + row_blocks - 1) / row_blocks;
+    c = c < 1 ? 1 : (c > max_chunks ? max_chunks : c);
+    const int64_t per = (n + c - 1) / c;
+    const int64_t chunk_len = (per + kRowTile - 1) / kRowTile * kRowTile;
+    const int chunks = (int)((n + chunk_len - 1) / chunk_len);
+    hipLaunchKernelGGL(k_potential_rows, dim3((unsigned)row_blocks, (unsigned)chunks),
+                       dim3(kRowTile), 0, s, pos, mass, n, chunk_len, part);
+    hipLaunchKernelGGL(k_potential_merge, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, part,
+                       chunks, mass, n, G, rows);
     return hipGetLastError();
 }
 
