@@ -179,7 +179,8 @@ Tile pick_tile(int kind, int prec, int64_t n)
 struct Layout {
     size_t flags = 0, part = 0, alt = 0, gm = 0, perm = 0, nmaj = 0, offs = 0, pos_c = 0, vel_c = 0,
            mass_c = 0, alt_c = 0, rows = 0, units = 0, bchunks = 0, ck = 0, seg = 0, lam_r = 0,
-           lam_v = 0, g_m = 0, u = 0, vtmp = 0, rk_vs = 0, rk_sr = 0, rk_sv = 0, total = 0;
+           lam_v = 0, g_m = 0, u = 0, vtmp = 0, rk_vs = 0, rk_sr = 0, rk_sv = 0, seg2 = 0,
+           part2 = 0, vtmp2 = 0, total = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -234,6 +235,11 @@ Layout layout(int op, int64_t n, int32_t ns, int64_t steps, int64_t K, int prec)
         const int64_t nck = (steps + K - 1) / K;
         L.ck = a.take((size_t)(nck + 1) * 6 * n * d);
         L.seg = a.take((size_t)std::min(K, std::max<int64_t>(steps, 1)) * 3 * n * d);
+        // the next segment's positions, recomputed on a second stream while the
+        // reverse sweep works on this one, with that stream's partials and velocity
+        L.seg2 = a.take((size_t)std::min(K, std::max<int64_t>(steps, 1)) * 3 * n * d);
+        L.part2 = a.take((size_t)cap * 3 * n * d);
+        L.vtmp2 = a.take(3 * n * d);
         L.lam_r = a.take(3 * n * d);
         L.lam_v = a.take(3 * n * d);
         L.g_m = a.take(n * d);
@@ -297,6 +303,34 @@ int capture_stream(hipStream_t* out)
         it = g_capture_streams.emplace(dev, s).first;
     }
     *out = it->second;
+    return NBODY_OK;
+}
+
+// A second stream per device (default priority, non-blocking) and the events
+// that order it against the caller's stream in the adjoint's pipelined reverse
+// sweep; g_adjoint_mu serialises the enqueue of adjoint calls, so the cached
+// events are recorded and waited on by one call at a time.
+struct SideStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t fwd = nullptr, ready[2] = {nullptr, nullptr}, freed[2] = {nullptr, nullptr};
+    std::mutex adjoint_mu;
+};
+std::map<int, std::unique_ptr<SideStream>> g_side;
+
+int side_stream(SideStream** out)
+{
+    int dev = 0;
+    NB_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_side.find(dev);
+    if (it == g_side.end()) {
+        auto ss = std::make_unique<SideStream>();
+        NB_HIP(hipStreamCreateWithFlags(&ss->stream, hipStreamNonBlocking));
+        for (hipEvent_t* e : {&ss->fwd, &ss->ready[0], &ss->ready[1], &ss->freed[0], &ss->freed[1]})
+            NB_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+        it = g_side.emplace(dev, std::move(ss)).first;
+    }
+    *out = it->second.get();
     return NBODY_OK;
 }
 
@@ -863,7 +897,14 @@ int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const doubl
     double* u = at<double>(workspace, L.u);
     double* vtmp = at<double>(workspace, L.vtmp);
     double* part = at<double>(workspace, L.part);
+    double* seg2 = at<double>(workspace, L.seg2);
+    double* part2 = at<double>(workspace, L.part2);
+    double* vtmp2 = at<double>(workspace, L.vtmp2);
     uint32_t* flags = at<uint32_t>(workspace, L.flags);
+    SideStream* side = nullptr;
+    NB_TRY(side_stream(&side));
+    std::lock_guard<std::mutex> adjoint_lock(side->adjoint_mu);
+    hipStream_t sb = side->stream;
     auto ck_r = [&](int64_t k) { return ck + k * 6 * n; };
     auto ck_v = [&](int64_t k) { return ck + k * 6 * n + 3 * n; };
 
@@ -892,22 +933,26 @@ int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const doubl
     const bool small = P.tile.variant == 3;
     const Tile vt = pick_tile(1, NBODY_FP64, n);
     const int vchunks = vjp_chunks(n, vt);
-    auto key_of = [&](uint64_t kind, int64_t kseg, uint64_t first) {
+    auto key_of = [&](uint64_t kind, int64_t kseg, uint64_t first, const double* segp) {
         GraphKey key;
         key.v = {kind, (uint64_t)kseg, first, (uint64_t)n, bits(G), bits(dt),
                  (uint64_t)P.tile.tpl, (uint64_t)P.tile.waves, (uint64_t)P.tile.chunks,
                  (uint64_t)P.tile.variant, (uint64_t)vt.tpl, (uint64_t)vt.waves,
                  (uint64_t)vt.chunks, ptrbits(mass), ptrbits(P.gm), ptrbits(part), ptrbits(flags),
-                 ptrbits(w0), ptrbits(w1), ptrbits(wv), ptrbits(seg), ptrbits(lam_r),
-                 ptrbits(lam_v), ptrbits(g_m)};
+                 ptrbits(w0), ptrbits(w1), ptrbits(wv), ptrbits(segp), ptrbits(lam_r),
+                 ptrbits(lam_v), ptrbits(g_m), ptrbits(part2), ptrbits(vtmp2)};
         return key;
     };
     // segments longer than this run their launches directly instead of from
     // a graph (a graph is captured once per segment length and replayed)
     constexpr int64_t kMaxGraphSegment = 1024;
+    auto maybe_graph_on = [&](hipStream_t st, const GraphKey& key, int64_t kseg,
+                              auto&& body) -> int {
+        if (kseg <= kMaxGraphSegment) return run_graph(key, st, body);
+        return body(st);
+    };
     auto maybe_graph = [&](const GraphKey& key, int64_t kseg, auto&& body) -> int {
-        if (kseg <= kMaxGraphSegment) return run_graph(key, s, body);
-        return body(s);
+        return maybe_graph_on(s, key, kseg, body);
     };
     NB_HIP(launch_scale(mass, G, n, gm, s));
     NB_HIP(hipMemcpyAsync(ck_r(0), pos0, b3, hipMemcpyDeviceToDevice, s));
@@ -921,7 +966,7 @@ int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const doubl
             NB_HIP(launch_run_small(0, P.tile, w0, w0, wv, mass, n, nullptr, G, dt, 0, kseg, kseg,
                                     nullptr, nullptr, flags, s));
         } else {
-            NB_TRY(maybe_graph(key_of(2, kseg, 0), kseg, [&](hipStream_t cs) {
+            NB_TRY(maybe_graph(key_of(2, kseg, 0, seg), kseg, [&](hipStream_t cs) {
                 for (int64_t i = 0; i <= kseg; ++i) {
                     const int st = step_launch(P, i, kseg, cs);
                     if (st != NBODY_OK) return st;
@@ -948,31 +993,67 @@ int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const doubl
         NB_HIP(launch_vjp(vt, ck_r(nck), mass, lam_v, 0.5 * dt, n, G, part, s));
         NB_HIP(launch_vjp_reduce(part, vchunks, n, lam_r, g_m, lam_v, dt, true, s));
     }
+    // Segments in reverse order, pipelined over two streams: the side stream
+    // recomputes the positions of segment c - 1 (from its checkpoint, into the
+    // other segment buffer, with its own partials and velocity) while the
+    // caller's stream runs the reverse sweep of segment c.  Events order a
+    // buffer's recompute after the sweep that last read it and before the
+    // sweep that reads it.
     StepPlan R = P;   // recompute plan: positions of one segment into seg slots
-    R.vel = vtmp;
-    for (int64_t c = nck - 1; c >= 0; --c) {
+    R.vel = vtmp2;
+    R.part = part2;
+    double* segbuf[2] = {seg, seg2};
+    bool freed_recorded[2] = {false, false};
+    auto recompute = [&](int64_t c) -> int {
+        const int b = (int)(c & 1);
         const int64_t kseg = std::min(K, steps - c * K);
-        NB_HIP(hipMemcpyAsync(seg, ck_r(c), b3, hipMemcpyDeviceToDevice, s));
-        NB_HIP(hipMemcpyAsync(vtmp, ck_v(c), b3, hipMemcpyDeviceToDevice, s));
-        NB_TRY(maybe_graph(key_of(3, kseg, c == 0), kseg, [&](hipStream_t cs) -> int {
-            // positions r_{cK+1} .. r_{cK+kseg-1} of the segment into seg slots
+        double* sg = segbuf[b];
+        if (freed_recorded[b]) NB_HIP(hipStreamWaitEvent(sb, side->freed[b], 0));
+        NB_HIP(hipMemcpyAsync(sg, ck_r(c), b3, hipMemcpyDeviceToDevice, sb));
+        NB_HIP(hipMemcpyAsync(vtmp2, ck_v(c), b3, hipMemcpyDeviceToDevice, sb));
+        NB_TRY(maybe_graph_on(sb, key_of(3, kseg, 0, sg), kseg, [&](hipStream_t cs) -> int {
+            // positions r_{cK+1} .. r_{cK+kseg-1} of the segment into its slots
             if (small && kseg >= 2)
-                NB_HIP(launch_run_small(0, R.tile, seg, nullptr, vtmp, mass, n, nullptr, G, dt, 0,
-                                        kseg - 2, kseg, nullptr, seg + 3 * n, flags, cs));
+                NB_HIP(launch_run_small(0, R.tile, sg, nullptr, vtmp2, mass, n, nullptr, G, dt, 0,
+                                        kseg - 2, kseg, nullptr, sg + 3 * n, flags, cs));
             for (int64_t k = 0; !small && k + 1 < kseg; ++k) {
-                double* pin = seg + k * 3 * n;
+                double* pin = sg + k * 3 * n;
                 NB_TRY(force_and_step(R, pin, pin + 3 * n, (k > 0 ? kClose : 0) | kOpen, cs));
             }
+            return (int)NBODY_OK;
+        }));
+        NB_HIP(hipEventRecord(side->ready[b], sb));
+        return NBODY_OK;
+    };
+    auto sweep = [&](int64_t c) -> int {
+        const int b = (int)(c & 1);
+        const int64_t kseg = std::min(K, steps - c * K);
+        const double* sg = segbuf[b];
+        NB_HIP(hipStreamWaitEvent(s, side->ready[b], 0));
+        NB_TRY(maybe_graph(key_of(4, kseg, c == 0, sg), kseg, [&](hipStream_t cs) -> int {
             for (int64_t k = kseg - 1; k >= 0; --k) {
                 const int64_t i = c * K + k;
                 // kick v_{i+1/2} = v_{i-1/2} + dt a(r_i)   (dt/2 for i = 0); the
                 // drift r_i = r_{i-1} + dt v_{i-1/2} before it (i > 0)
-                NB_HIP(launch_vjp(vt, seg + k * 3 * n, mass, lam_v, i > 0 ? dt : 0.5 * dt, n, G,
+                NB_HIP(launch_vjp(vt, sg + k * 3 * n, mass, lam_v, i > 0 ? dt : 0.5 * dt, n, G,
                                   part, cs));
                 NB_HIP(launch_vjp_reduce(part, vchunks, n, lam_r, g_m, lam_v, dt, i > 0, cs));
             }
             return (int)NBODY_OK;
         }));
+        NB_HIP(hipEventRecord(side->freed[b], s));
+        freed_recorded[b] = true;
+        return NBODY_OK;
+    };
+    if (nck > 0) {
+        // the checkpoints (forward run, above) and G m come before any recompute
+        NB_HIP(hipEventRecord(side->fwd, s));
+        NB_HIP(hipStreamWaitEvent(sb, side->fwd, 0));
+        NB_TRY(recompute(nck - 1));
+        for (int64_t c = nck - 1; c >= 0; --c) {
+            if (c > 0) NB_TRY(recompute(c - 1));
+            NB_TRY(sweep(c));
+        }
     }
     NB_HIP(hipMemcpyAsync(grad_pos0, lam_r, b3, hipMemcpyDeviceToDevice, s));
     NB_HIP(hipMemcpyAsync(grad_vel0, lam_v, b3, hipMemcpyDeviceToDevice, s));
