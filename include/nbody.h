@@ -123,7 +123,11 @@ int32_t nbody_rk4_run(double* pos, double* vel, const double* mass,
  * Outputs grad_pos0, grad_vel0 ([3n]) and grad_mass ([n]); pos_out/vel_out
  * ([3n], may be NULL) receive r_T, v_T.  The forward run is stored every
  * checkpoint_every steps and recomputed segment by segment during the
- * reverse sweep.  Inputs are not modified.  checkpoint_every >= 1. */
+ * reverse sweep; the library recomputes the next segment on a second stream
+ * of its own (default priority) while `stream` sweeps the current one, and
+ * every piece of that work is ordered before later work on `stream`.
+ * Calls on one device enqueue one at a time.  Inputs are not modified.
+ * checkpoint_every >= 1. */
 int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const double* mass,
                              int64_t n, double G, double dt, int64_t steps,
                              int64_t checkpoint_every,
