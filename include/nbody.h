@@ -173,7 +173,8 @@ int32_t nbody_get_flags(void* workspace, void* stream, int32_t clear, int32_t* f
  * workgroup (1, 2, 4, 8), source chunks (1..64) and how sources reach the
  * lanes (variant 0: staged through LDS; 1: read once per wavefront into
  * scalar registers; 2: as 1, the waves of a workgroup sharing targets and
- * splitting the sources; the adjoint pass supports variant 0 only).
+ * splitting the sources; the adjoint pass supports variants 0 and 1 and
+ * defaults to 1).
  * Variant 3 (kind 0 only, n <= 512, targets_per_lane = 1, waves = 16):
  * one workgroup holds the system in LDS and runs whole steps, force pass,
  * reduction and kick-drift-kick, in one launch; chunks is then the number

@@ -147,13 +147,11 @@ Tile heuristic_tile(int kind, int prec, int64_t n)
         return Tile{4, 4, 1, 5};
     if (kind == 0) return force_only_tile(prec, n);
     if (kind == 1) {
-        // transpose-Jacobian pass: one wave per 64 targets, sources split in
-        // chunks of >= 16 until about 4096 waves are in flight
-        const int64_t tb = (n + 63) / 64;
-        const int64_t c = std::min<int64_t>({std::max<int64_t>(1, 4096 / tb),
-                                             std::max<int64_t>(1, n / 16),
+        // transpose-Jacobian pass: scalar-operand sources, two waves per 128
+        // targets, sources split in up to 64 chunks of >= 16
+        const int64_t c = std::min<int64_t>({64, std::max<int64_t>(1, n / 16),
                                              (int64_t)chunk_cap(n)});
-        return Tile{1, 1, (int)c, 0};
+        return Tile{1, 2, (int)c, 1};
     }
     return Tile{1, 1, 1, 0};
 }
@@ -850,7 +848,7 @@ int32_t nbody_set_tile(int32_t kind, int32_t precision, int64_t n, const nbody_t
     NB_TRY(check_prec(precision, 0.0));
     if (kind == 2) n = 0;
     Tile t{tile_host->targets_per_lane, tile_host->waves, tile_host->chunks, tile_host->variant};
-    if (!tile_supported(t) || (kind == 1 && (t.tpl > 2 || t.waves > 4 || t.variant != 0)) ||
+    if (!tile_supported(t) || (kind == 1 && (t.tpl > 2 || t.waves > 4 || t.variant > 1)) ||
         (t.variant == 3 && (kind != 0 || n > kSmallMax)) || (t.variant == 4 && kind != 0) ||
         (t.variant == 5 && !mutual_fits(kind, precision, n)))
         return fail(NBODY_EINVAL, "unsupported tile (%d, %d, %d, variant %d) for kind %d",
@@ -1539,7 +1537,7 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
     const int waves[4] = {1, 2, 4, 8};
     for (int it = 0; it < 3; ++it)
         for (int iw = 0; iw < 4; ++iw) {
-            for (int variant = 0; variant < (kind == 0 ? 3 : 1); ++variant) {
+            for (int variant = 0; variant < (kind == 0 ? 3 : 2); ++variant) {
                 Tile t{tpls[it], waves[iw], 1, variant};
                 if (kind == 1 && (t.tpl > 2 || t.waves > 4)) continue;
                 if (variant != 0 && t.tpl == 4 && t.waves == 8) continue;   // register spills

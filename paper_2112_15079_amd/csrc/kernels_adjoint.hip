@@ -132,6 +132,116 @@ __global__ __launch_bounds__(64 * W) void k_vjp(const double* __restrict__ pos,
     }
 }
 
+// Scalar-operand form (tile variant 1): every lane of a wavefront needs the
+// same source, so the wave reads kVG sources at a time from the planes at a
+// uniform index (scalar loads; no LDS, no barriers) and sweeps its chunk.
+// The product is linear in the cotangent, so it runs on lam and the outputs
+// are scaled by cu.
+constexpr int kVG = 4;
+
+template <int T, bool MASK>
+__device__ __forceinline__ void vjp_pair(double sx, double sy, double sz, double sm, double sux,
+                                         double suy, double suz, int64_t j, const double (&qx)[T],
+                                         const double (&qy)[T], const double (&qz)[T],
+                                         const double (&qm)[T], const double (&ux)[T],
+                                         const double (&uy)[T], const double (&uz)[T],
+                                         const int64_t (&qid)[T], double (&ox)[T],
+                                         double (&oy)[T], double (&oz)[T], double (&og)[T])
+{
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const double dx = sx - qx[t];
+        const double dy = sy - qy[t];
+        const double dz = sz - qz[t];
+        const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+        const double y = rinv_f64(r2);
+        const double y2 = y * y;
+        double i3 = y * y2;
+        double i5 = i3 * y2;
+        if (MASK) {
+            const bool self = (j == qid[t]);
+            i3 = self ? 0.0 : i3;
+            i5 = self ? 0.0 : i5;
+        }
+        const double wx = __builtin_fma(-sm, ux[t], qm[t] * sux);
+        const double wy = __builtin_fma(-sm, uy[t], qm[t] * suy);
+        const double wz = __builtin_fma(-sm, uz[t], qm[t] * suz);
+        const double dw = __builtin_fma(dz, wz, __builtin_fma(dy, wy, dx * wx));
+        const double c = 3.0 * dw * i5;
+        ox[t] = __builtin_fma(-c, dx, __builtin_fma(wx, i3, ox[t]));
+        oy[t] = __builtin_fma(-c, dy, __builtin_fma(wy, i3, oy[t]));
+        oz[t] = __builtin_fma(-c, dz, __builtin_fma(wz, i3, oz[t]));
+        const double ud = __builtin_fma(suz, dz, __builtin_fma(suy, dy, sux * dx));
+        og[t] = __builtin_fma(ud, i3, og[t]);
+    }
+}
+
+template <int T, int W>
+__global__ __launch_bounds__(64 * W) void k_vjp_s(const double* __restrict__ pos,
+                                                  const double* __restrict__ mass,
+                                                  const double* __restrict__ lam, double cu,
+                                                  int64_t n, int64_t chunk_len, double G,
+                                                  double* __restrict__ part)
+{
+    constexpr int NT = 64 * W;
+    const int tid = threadIdx.x;
+    const int64_t tb0 = (int64_t)blockIdx.x * NT * T;
+    const int64_t c = blockIdx.y;
+    const int64_t jbeg = c * chunk_len;
+    const int64_t jend = (jbeg + chunk_len < n) ? jbeg + chunk_len : n;
+
+    double qx[T], qy[T], qz[T], qm[T], ux[T], uy[T], uz[T];
+    double ox[T], oy[T], oz[T], og[T];
+    int64_t qid[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int64_t p = tb0 + (int64_t)t * NT + tid;
+        const int64_t q = p < n ? p : n - 1;
+        qid[t] = p;
+        qx[t] = pos[q]; qy[t] = pos[n + q]; qz[t] = pos[2 * n + q];
+        qm[t] = mass[q];
+        ux[t] = lam[q]; uy[t] = lam[n + q]; uz[t] = lam[2 * n + q];
+        ox[t] = 0.0; oy[t] = 0.0; oz[t] = 0.0; og[t] = 0.0;
+    }
+    const int64_t tend = tb0 + (int64_t)NT * T;
+    int64_t j = jbeg;
+    for (; j + kVG <= jend; j += kVG) {   // whole groups: contiguous scalar loads
+        double xs[kVG], ys[kVG], zs[kVG], ms[kVG], uxs[kVG], uys[kVG], uzs[kVG];
+#pragma unroll
+        for (int u = 0; u < kVG; ++u) {
+            xs[u] = pos[j + u]; ys[u] = pos[n + j + u]; zs[u] = pos[2 * n + j + u];
+            ms[u] = mass[j + u];
+            uxs[u] = lam[j + u]; uys[u] = lam[n + j + u]; uzs[u] = lam[2 * n + j + u];
+        }
+        if ((j < tend) && (tb0 < j + kVG)) {
+#pragma unroll
+            for (int u = 0; u < kVG; ++u)
+                vjp_pair<T, true>(xs[u], ys[u], zs[u], ms[u], uxs[u], uys[u], uzs[u], j + u, qx,
+                                  qy, qz, qm, ux, uy, uz, qid, ox, oy, oz, og);
+        } else {
+#pragma unroll
+            for (int u = 0; u < kVG; ++u)
+                vjp_pair<T, false>(xs[u], ys[u], zs[u], ms[u], uxs[u], uys[u], uzs[u], j + u, qx,
+                                   qy, qz, qm, ux, uy, uz, qid, ox, oy, oz, og);
+        }
+    }
+    for (; j < jend; ++j)   // the chunk's ragged end
+        vjp_pair<T, true>(pos[j], pos[n + j], pos[2 * n + j], mass[j], lam[j], lam[n + j],
+                          lam[2 * n + j], j, qx, qy, qz, qm, ux, uy, uz, qid, ox, oy, oz, og);
+    double* pc = part + c * 4 * n;
+    const double gc = G * cu;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int64_t p = tb0 + (int64_t)t * NT + tid;
+        if (p < n) {
+            pc[p] = gc * ox[t];
+            pc[n + p] = gc * oy[t];
+            pc[2 * n + p] = gc * oz[t];
+            pc[3 * n + p] = -gc * og[t];
+        }
+    }
+}
+
 constexpr int kBlock = 256;
 
 // lam_r += sum of the chunk partials of planes 0..2, g_m += plane 3; then,
@@ -224,6 +334,16 @@ static hipError_t vjp_tw(const double* pos, const double* mass, const double* la
     return hipGetLastError();
 }
 
+template <int T, int W>
+static hipError_t vjp_s_tw(const double* pos, const double* mass, const double* lam, double cu,
+                           int64_t n, int64_t L, int chunks, double G, double* part, hipStream_t s)
+{
+    constexpr int NT = 64 * W;
+    const dim3 grid((unsigned)((n + (int64_t)NT * T - 1) / ((int64_t)NT * T)), (unsigned)chunks);
+    hipLaunchKernelGGL((k_vjp_s<T, W>), grid, dim3(NT), 0, s, pos, mass, lam, cu, n, L, G, part);
+    return hipGetLastError();
+}
+
 static constexpr int64_t kVjpGranule = 8;
 
 int64_t vjp_chunk_length(int64_t n, const Tile& t)
@@ -241,12 +361,13 @@ int vjp_chunks(int64_t n, const Tile& t)
 hipError_t launch_vjp(const Tile& tile, const double* pos, const double* mass, const double* lam,
                       double cu, int64_t n, double G, double* part, hipStream_t s)
 {
-    if (tile.variant != 0) return hipErrorInvalidValue;
+    if (tile.variant != 0 && tile.variant != 1) return hipErrorInvalidValue;
     const int64_t L = vjp_chunk_length(n, tile);
     const int chunks = vjp_chunks(n, tile);
 #define NB_CASE(TT, WW)                                                                 \
     if (tile.tpl == TT && tile.waves == WW)                                             \
-        return vjp_tw<TT, WW>(pos, mass, lam, cu, n, L, chunks, G, part, s);
+        return tile.variant == 1 ? vjp_s_tw<TT, WW>(pos, mass, lam, cu, n, L, chunks, G, part, s) \
+                                 : vjp_tw<TT, WW>(pos, mass, lam, cu, n, L, chunks, G, part, s);
     NB_CASE(1, 1) NB_CASE(1, 2) NB_CASE(1, 4) NB_CASE(2, 1) NB_CASE(2, 2) NB_CASE(2, 4)
 #undef NB_CASE
     return hipErrorInvalidValue;

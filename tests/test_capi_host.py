@@ -163,7 +163,16 @@ def test_tile_table():
     assert lib.nbody_get_tile(0, 0, 10425, ctypes.byref(t)) == C.NBODY_OK
     assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == (1, 2, 9, 1)
     assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(1, 2, 9, 3))) == C.NBODY_EINVAL
-    assert lib.nbody_set_tile(1, 0, 100, ctypes.byref(C.Tile(1, 1, 1, 1))) == C.NBODY_EINVAL
+    # the adjoint pass defaults to scalar operands, 2 waves, up to 64 source
+    # chunks of >= 16 bodies, within the workspace's chunk cap
+    for n, want in ((20, (1, 2, 1, 1)), (100, (1, 2, 6, 1)), (2079, (1, 2, 64, 1)),
+                    (131072, (1, 2, 32, 1))):
+        assert lib.nbody_get_tile(1, 0, n, ctypes.byref(t)) == C.NBODY_OK
+        assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == want, n
+    # it takes variants 0 (LDS tiles) and 1 (scalar operands) only
+    assert lib.nbody_set_tile(1, 0, 100, ctypes.byref(C.Tile(1, 1, 1, 1))) == C.NBODY_OK
+    assert lib.nbody_get_tile(1, 0, 100, ctypes.byref(t)) == C.NBODY_OK and t.variant == 1
+    assert lib.nbody_set_tile(1, 0, 100, ctypes.byref(C.Tile(1, 1, 1, 2))) == C.NBODY_EINVAL
     assert lib.nbody_set_tile(2, 0, 0, ctypes.byref(C.Tile(2, 1, 16, 1))) == C.NBODY_OK
     assert lib.nbody_get_tile(2, 0, 0, ctypes.byref(t)) == C.NBODY_OK and t.variant == 1
     assert lib.nbody_set_tile(3, 0, 10, ctypes.byref(C.Tile(1, 1, 1, 0))) == C.NBODY_EINVAL
@@ -189,7 +198,7 @@ def test_tile_table_single_workgroup_variant():
         assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == (1, 8, 1, 4)
         assert lib.nbody_get_tile(0, prec, 600, ctypes.byref(t)) == C.NBODY_OK and t.variant < 3
     assert lib.nbody_get_tile(0, 0, 16, ctypes.byref(t)) == C.NBODY_OK and t.chunks == 16
-    assert lib.nbody_get_tile(1, 0, 131, ctypes.byref(t)) == C.NBODY_OK and t.variant == 0
+    assert lib.nbody_get_tile(1, 0, 131, ctypes.byref(t)) == C.NBODY_OK and t.variant == 1
     assert lib.nbody_get_tile(2, 0, 0, ctypes.byref(t)) == C.NBODY_OK and t.variant != 3
     assert lib.nbody_set_tile(0, 0, 400, ctypes.byref(C.Tile(1, 16, 2, 3))) == C.NBODY_OK
     assert lib.nbody_get_tile(0, 0, 400, ctypes.byref(t)) == C.NBODY_OK

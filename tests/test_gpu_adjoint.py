@@ -76,7 +76,8 @@ def test_adjoint_pipelined_segments_bitwise():
 
 
 @pytest.mark.parametrize("vtile", [(1, 1, 1, 0), (2, 1, 3, 0), (1, 4, 5, 0), (2, 2, 64, 0),
-                                   (1, 1, 64, 0), (1, 2, 17, 0)])
+                                   (1, 1, 64, 0), (1, 2, 17, 0), (1, 1, 1, 1), (2, 1, 3, 1),
+                                   (1, 4, 5, 1), (1, 1, 64, 1), (2, 2, 17, 1)])
 @pytest.mark.parametrize("n_small", [20, 150])
 def test_adjoint_transpose_pass_tiles(vtile, n_small):
     """The transpose-Jacobian pass over tile shapes and source chunkings
