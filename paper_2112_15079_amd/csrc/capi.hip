@@ -105,10 +105,11 @@ bool mutual_fits(int kind, int prec, int64_t n)
 }
 
 // Partial slots of a single system's workspace: the one-way passes' chunks,
-// or one per range where the each-pair-once pass may run.
+// or one per range (plus the extra slots of a split last round) where the
+// each-pair-once pass may run.
 int part_slots(int64_t n)
 {
-    return std::max(chunk_cap(n), n <= kMutualMaxN ? mutual_ranges(n) : 0);
+    return std::max(chunk_cap(n), n <= kMutualMaxN ? mutual_slots(n, 4, 4) : 0);
 }
 
 // Defaults from tile sweeps on MI355X (the autotuner refines them): one

@@ -25,7 +25,7 @@ struct Tile {
                       //    and drift in the same kernel (tpl 1, 2; waves 2, 4, 8);
                       // 5: each unordered pair once ((tpl, waves) = (1, 4),
                       //    (2, 2), (2, 4), (4, 4); chunks = 1: the pass writes
-                      //    mutual_ranges(n) partials)
+                      //    mutual_slots(n, tpl, waves) partials)
 };
 
 constexpr int kMaxChunks = 64;
@@ -82,6 +82,9 @@ hipError_t launch_force_batched(int precision, const Tile& tile, const double* p
 // Ranges of 4 blocks of 64 bodies; the pass writes one partial per range and
 // body (slot order = range order), summed by the ordinary step epilogue.
 int mutual_ranges(int64_t n);
+// Partial slots of a single system's pass: the ranges, plus the extra slots
+// of the split last round (shape (4, 4) only).
+int mutual_slots(int64_t n, int tpl, int waves);
 bool mutual_shape_supported(int tpl, int waves);
 hipError_t launch_force_mutual(int precision, int tpl, int waves, const double* pos,
                                const double* gm, int64_t n, const int64_t* nmaj, double* part,

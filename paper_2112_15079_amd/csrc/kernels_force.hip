@@ -662,7 +662,7 @@ static hipError_t launch_batched_tw(int precision, int variant, const double* po
 
 int effective_chunks(int64_t n, const Tile& t)
 {
-    if (t.variant == 5) return mutual_ranges(n);
+    if (t.variant == 5) return mutual_slots(n, t.tpl, t.waves);
     const int64_t L = chunk_length(n, t);
     return (int)((n + L - 1) / L);
 }

@@ -40,6 +40,20 @@
 // source, slot s > R as a target and slot R from the diagonal workgroup:
 // every slot exactly once.  An ensemble runs the same workgroups per system,
 // listed as units (system, g, r), on planes spanning all systems.
+//
+// The last round (single systems, shape (4, 4)): the pass takes about one
+// period per ceil(pairs / 256) rounds of workgroups, one per CU per round.
+// When the pairs past the last whole round are few (at most 128), those
+// pairs are each run as two workgroups of half the work, so the partly
+// filled round costs half a period: a half holds two of the four target
+// blocks (two per lane) against all four source blocks, one per wave.  The
+// halves' targets are disjoint; their reactions on the same sources are
+// not, so the second half writes them to an extra slot.  The split pairs
+// are those on the super-diagonals r - g = 1 .. D - 1 and the first kD of
+// r - g = D; the extra slot of pair (g, g + d) is R + d - 1, and the
+// diagonal workgroup of each range writes zeros to the extra slots that no
+// split pair fills, so every body still receives each of its R + D slots
+// exactly once.
 #include "common.hpp"
 #include "pair_math.hpp"
 
@@ -286,20 +300,188 @@ __device__ __forceinline__ void sweep_dispatch32(int d, const double* px, const 
     }
 }
 
+// Which workgroups run whole range pairs and which run halves (see the top
+// of the file).  D = 0: every pair whole.
+struct MutualTail {
+    int R;    // ranges
+    int F;    // workgroups running whole pairs (a multiple of 256 when D > 0)
+    int D;    // split pairs lie on super-diagonals 1 .. D
+    int kD;   // ... on super-diagonal D only those with g < kD
+};
+
+// Split pairs in row g: (g, g + 1) .. (g, g + s(g)).
+__host__ __device__ inline int mt_split_in_row(const MutualTail& t, int g)
+{
+    if (t.D == 0) return 0;
+    const int a = t.D - 1 < t.R - 1 - g ? t.D - 1 : t.R - 1 - g;
+    return a + (g < t.kD ? 1 : 0);
+}
+
+// Whole pairs in rows 0 .. g-1 (each row: R - y pairs, s(y) of them split).
+__host__ __device__ inline int64_t mt_row_start(const MutualTail& t, int g)
+{
+    int64_t c = (int64_t)g * t.R - (int64_t)g * (g - 1) / 2;
+    if (t.D == 0) return c;
+    const int a = g < t.R - t.D + 1 ? g : t.R - t.D + 1;   // rows holding all D - 1
+    c -= (int64_t)(t.D - 1) * a;
+    for (int y = a; y < g; ++y) c -= t.R - 1 - y;
+    c -= g < t.kD ? g : t.kD;
+    return c;
+}
+
+// Workgroup bid -> pair (g, r) and half (-1: whole; 0, 1: the halves of a
+// split pair, the second writing its reactions to extra slot xslot).
+__host__ __device__ inline void mt_decode(const MutualTail& tl, int64_t bid, int& g, int& r,
+                                          int& half, int& xslot)
+{
+    if (bid >= tl.F) {   // the halves of the split pairs, super-diagonal by super-diagonal
+        const int64_t h = bid - tl.F;
+        int u = (int)(h >> 1), d = 1;
+        while (d < tl.D && u >= tl.R - d) {
+            u -= tl.R - d;
+            ++d;
+        }
+        g = u;
+        r = u + d;
+        half = (int)(h & 1);
+        xslot = tl.R + d - 1;
+        return;
+    }
+    // the whole pairs (g, r), r >= g, row by row without the split ones: row
+    // g from the quadratic's root for the full triangle (row start
+    // g R - g(g-1)/2), then the last row starting at or before bid
+    const double R2 = 2.0 * tl.R + 1.0;
+    g = (int)((R2 - __builtin_sqrt(R2 * R2 - 8.0 * (double)bid)) * 0.5);
+    g = g < 0 ? 0 : (g > tl.R - 1 ? tl.R - 1 : g);
+    while (g > 0 && mt_row_start(tl, g) > bid) --g;
+    while (g < tl.R - 1 && mt_row_start(tl, g + 1) <= bid) ++g;
+    const int idx = (int)(bid - mt_row_start(tl, g));
+    r = idx == 0 ? g : g + mt_split_in_row(tl, g) + idx;
+    half = -1;
+    xslot = 0;
+}
+
+// Half `half` of the split pair (g, r), r > g: target blocks 4g + 2 half and
+// 4g + 2 half + 1 (two per lane) against source block 4r + w in wave w.  The
+// LDS arrays are the whole-pair workgroup's (same sizes or larger).
+template <bool SPLIT>
+__device__ __forceinline__ void mutual_half_body(const double* __restrict__ pos,
+                                                 const double* __restrict__ gm, int64_t n,
+                                                 int64_t n_major, int g, int r, int half,
+                                                 int xslot, double* __restrict__ part,
+                                                 double (*sx)[128], double (*sy)[128],
+                                                 double (*sz)[128], double (*sg)[128],
+                                                 float (*sgf)[128], double (*racc)[3][64],
+                                                 double* combp)
+{
+    constexpr int KT = 2;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int nb = (int)((n + 63) / 64);
+    const int I0 = g * kMM + 2 * half;
+    const int J = r * kMM + w;
+    const int64_t plane = 3 * n;
+
+    Body tg[KT];
+    float tgf[KT];
+    double ax[KT], ay[KT], az[KT];
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+        tg[t] = load_body(pos, gm, n, n, (int64_t)(I0 + t) * 64 + lane);
+        tgf[t] = (float)tg[t].gm;
+        ax[t] = 0.0; ay[t] = 0.0; az[t] = 0.0;
+    }
+    {
+        const Body b = load_body(pos, gm, n, n, (int64_t)J * 64 + lane);
+        const int a0 = 32 * (lane >> 4) + (lane & 15);
+        sx[w][a0] = b.x; sx[w][a0 + 16] = b.x;
+        sy[w][a0] = b.y; sy[w][a0 + 16] = b.y;
+        sz[w][a0] = b.z; sz[w][a0 + 16] = b.z;
+        sg[w][a0] = b.gm; sg[w][a0 + 16] = b.gm;
+        if (SPLIT) {
+            sgf[w][a0] = (float)b.gm;
+            sgf[w][a0 + 16] = (float)b.gm;
+        }
+        racc[w][0][lane] = 0.0;
+        racc[w][1][lane] = 0.0;
+        racc[w][2][lane] = 0.0;
+    }
+    const bool fp32 = SPLIT && I0 >= (int)((n_major + 63) / 64);
+    __syncthreads();
+    if (J < nb) {   // r > g: J - I0 >= 2, every tile both ways
+        if (fp32)
+            sweep_dispatch32<KT>(J - I0, sx[w], sy[w], sz[w], sgf[SPLIT ? w : 0], &racc[w][0][0],
+                                 lane, tg, tgf, ax, ay, az);
+        else
+            sweep_dispatch<KT>(J - I0, sx[w], sy[w], sz[w], sg[w], &racc[w][0][0], lane, tg, ax,
+                               ay, az, PolyConst{vreg_const(1.875), vreg_const(1.5)});
+    }
+    // the four waves' target sums, added in wave order
+    double (*comb)[KT][3][64] = reinterpret_cast<double (*)[KT][3][64]>(combp);
+    if (w > 0) {
+#pragma unroll
+        for (int t = 0; t < KT; ++t) {
+            comb[w - 1][t][0][lane] = ax[t];
+            comb[w - 1][t][1][lane] = ay[t];
+            comb[w - 1][t][2][lane] = az[t];
+        }
+    }
+    __syncthreads();
+    if (w == 0) {
+        for (int o = 0; o < 3; ++o) {
+#pragma unroll
+            for (int t = 0; t < KT; ++t) {
+                ax[t] += comb[o][t][0][lane];
+                ay[t] += comb[o][t][1][lane];
+                az[t] += comb[o][t][2][lane];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < KT; ++t) {
+            const int64_t i = (int64_t)(I0 + t) * 64 + lane;
+            if (i < n) {
+                double* pt = part + (int64_t)r * plane;
+                pt[i] = ax[t];
+                pt[n + i] = ay[t];
+                pt[2 * n + i] = az[t];
+            }
+        }
+    }
+    const int64_t j = (int64_t)J * 64 + lane;
+    if (j < n) {
+        double* ps = part + (int64_t)(half == 0 ? g : xslot) * plane;
+        ps[j] = racc[w][0][lane];
+        ps[n + j] = racc[w][1][lane];
+        ps[2 * n + j] = racc[w][2][lane];
+    }
+}
+
 // Workgroup (g, r) of a system of n bodies: pos, gm and part start at the
 // system's first body, coordinate and partial planes are `stride` apart
 // (partial slot c of component k of body i at part[(3c + k) stride + i]).
+// half >= 0 runs that half of a split pair instead (single systems, stride
+// n, shape (4, 4)); the diagonal workgroup zero-fills the extra slots of
+// `tl` that no split pair writes.
 template <int KMT, int KMW, bool SPLIT>
 __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
                                             const double* __restrict__ gm, int64_t n,
                                             int64_t stride, int64_t n_major, int g, int r,
-                                            double* __restrict__ part)
+                                            double* __restrict__ part, const MutualTail& tl,
+                                            int half, int xslot)
 {
     using Shape = MutualShape<KMT, KMW>;
     __shared__ double sx[kMM][128], sy[kMM][128], sz[kMM][128], sg[kMM][128];
     __shared__ float sgf[SPLIT ? kMM : 1][128];
     __shared__ double racc[kMM][3][64];
     __shared__ double comb[Shape::kShare > 1 ? Shape::kShare - 1 : 1][Shape::kSets][KMT][3][64];
+    if constexpr (KMT == 4 && KMW == 4) {
+        static_assert(sizeof(comb) >= 3 * 2 * 3 * 64 * sizeof(double), "half-pair sums fit");
+        if (half >= 0) {
+            mutual_half_body<SPLIT>(pos, gm, n, n_major, g, r, half, xslot, part, sx, sy, sz, sg,
+                                    SPLIT ? sgf : nullptr, racc, &comb[0][0][0][0][0]);
+            return;
+        }
+    }
 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -424,6 +606,14 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
                 pt[i] = ax[t] + racc[jb][0][lane];
                 pt[stride + i] = ay[t] + racc[jb][1][lane];
                 pt[2 * stride + i] = az[t] + racc[jb][2][lane];
+                // extra slot R + d - 1 is written by pair (g - d, g) if split
+                for (int d = 1; d <= tl.D; ++d) {
+                    if (g >= d && (d < tl.D || g - d < tl.kD)) continue;
+                    double* pz = part + (int64_t)(tl.R + d - 1) * plane;
+                    pz[i] = 0.0;
+                    pz[stride + i] = 0.0;
+                    pz[2 * stride + i] = 0.0;
+                }
             }
         }
     }
@@ -434,20 +624,12 @@ __global__ __launch_bounds__(64 * KMW) void k_force_mutual(const double* __restr
                                                            const double* __restrict__ gm,
                                                            int64_t n,
                                                            const int64_t* __restrict__ nmaj,
-                                                           int ranges, double* __restrict__ part)
+                                                           MutualTail tl,
+                                                           double* __restrict__ part)
 {
-    // blockIdx.x enumerates the pairs (g, r), r >= g, row by row: row g
-    // starts at S(g) = g*ranges - g(g-1)/2; g from the quadratic's root,
-    // corrected by at most a step either way for rounding
-    const int64_t bid = blockIdx.x;
-    const double R2 = 2.0 * ranges + 1.0;
-    int g = (int)((R2 - __builtin_sqrt(R2 * R2 - 8.0 * (double)bid)) * 0.5);
-    g = g < 0 ? 0 : (g > ranges - 1 ? ranges - 1 : g);
-    auto row_start = [&](int64_t x) { return x * ranges - x * (x - 1) / 2; };
-    if (g > 0 && row_start(g) > bid) --g;
-    if (g < ranges - 1 && row_start(g + 1) <= bid) ++g;
-    const int r = (int)(bid - row_start(g)) + g;
-    mutual_unit<KMT, KMW, SPLIT>(pos, gm, n, n, SPLIT ? nmaj[0] : 0, g, r, part);
+    int g, r, half, xslot;
+    mt_decode(tl, blockIdx.x, g, r, half, xslot);
+    mutual_unit<KMT, KMW, SPLIT>(pos, gm, n, n, SPLIT ? nmaj[0] : 0, g, r, part, tl, half, xslot);
 }
 
 // The ensemble: one workgroup per unit (system, g = tblock, r = chunk) of the
@@ -459,13 +641,51 @@ __global__ __launch_bounds__(64 * KMW) void k_force_mutual_batched(
     double* __restrict__ part)
 {
     const BatchUnit u = units[blockIdx.x];
+    const MutualTail whole{u.chunks, 0, 0, 0};
     mutual_unit<KMT, KMW, SPLIT>(pos + u.body0, gm + u.body0, u.n, n_total,
-                                 SPLIT ? nmaj[u.sys] : 0, u.tblock, u.chunk, part + u.body0);
+                                 SPLIT ? nmaj[u.sys] : 0, u.tblock, u.chunk, part + u.body0,
+                                 whole, -1, 0);
 }
 
 }  // namespace
 
 int mutual_ranges(int64_t n) { return (int)((((n + 63) / 64) + kMM - 1) / kMM); }
+
+// CUs of the device the split of the last round is laid out for (results
+// do not depend on the device).
+static constexpr int64_t kMutualCUs = 256;
+
+static MutualTail mutual_tail(int64_t n, int tpl, int waves)
+{
+    MutualTail t;
+    t.R = mutual_ranges(n);
+    const int64_t U = (int64_t)t.R * (t.R + 1) / 2;
+    const int64_t rem = U % kMutualCUs;
+    t.F = (int)U;
+    t.D = 0;
+    t.kD = 0;
+    // split only the pairs past the last whole round, when their halves fit
+    // in one round and they are off the diagonal
+    if (tpl != 4 || waves != 4 || U > 16 * kMutualCUs || rem == 0 || 2 * rem > kMutualCUs ||
+        rem > U - t.R)
+        return t;
+    int64_t left = rem;
+    int d = 1;
+    while (left > t.R - d) {
+        left -= t.R - d;
+        ++d;
+    }
+    t.D = d;
+    t.kD = (int)left;
+    t.F = (int)(U - rem);
+    return t;
+}
+
+int mutual_slots(int64_t n, int tpl, int waves)
+{
+    const MutualTail t = mutual_tail(n, tpl, waves);
+    return t.R + t.D;
+}
 
 bool mutual_shape_supported(int tpl, int waves)
 {
@@ -475,22 +695,22 @@ bool mutual_shape_supported(int tpl, int waves)
 
 template <bool SPLIT>
 static void launch_mutual_shape(int tpl, int waves, dim3 grid, const double* pos, const double* gm,
-                                int64_t n, const int64_t* nmaj, int ranges, double* part,
-                                hipStream_t s)
+                                int64_t n, const int64_t* nmaj, const MutualTail& tl,
+                                double* part, hipStream_t s)
 {
     const dim3 block((unsigned)(64 * waves));
     if (tpl == 1)
         hipLaunchKernelGGL((k_force_mutual<1, 4, SPLIT>), grid, block, 0, s, pos, gm, n, nmaj,
-                           ranges, part);
+                           tl, part);
     else if (tpl == 2 && waves == 2)
         hipLaunchKernelGGL((k_force_mutual<2, 2, SPLIT>), grid, block, 0, s, pos, gm, n, nmaj,
-                           ranges, part);
+                           tl, part);
     else if (tpl == 2)
         hipLaunchKernelGGL((k_force_mutual<2, 4, SPLIT>), grid, block, 0, s, pos, gm, n, nmaj,
-                           ranges, part);
+                           tl, part);
     else
         hipLaunchKernelGGL((k_force_mutual<4, 4, SPLIT>), grid, block, 0, s, pos, gm, n, nmaj,
-                           ranges, part);
+                           tl, part);
 }
 
 template <bool SPLIT>
@@ -537,12 +757,13 @@ hipError_t launch_force_mutual(int precision, int tpl, int waves, const double* 
 {
     if (!gm || n < 1 || !mutual_shape_supported(tpl, waves) || (precision != 0 && !nmaj))
         return hipErrorInvalidValue;
-    const int64_t ranges = mutual_ranges(n);
-    const dim3 grid((unsigned)(ranges * (ranges + 1) / 2));
+    const MutualTail tl = mutual_tail(n, tpl, waves);
+    const int64_t pairs = (int64_t)tl.R * (tl.R + 1) / 2;
+    const dim3 grid((unsigned)(tl.F + 2 * (pairs - tl.F)));   // whole pairs, then halves
     if (precision == 0)
-        launch_mutual_shape<false>(tpl, waves, grid, pos, gm, n, nullptr, (int)ranges, part, s);
+        launch_mutual_shape<false>(tpl, waves, grid, pos, gm, n, nullptr, tl, part, s);
     else
-        launch_mutual_shape<true>(tpl, waves, grid, pos, gm, n, nmaj, (int)ranges, part, s);
+        launch_mutual_shape<true>(tpl, waves, grid, pos, gm, n, nmaj, tl, part, s);
     return hipGetLastError();
 }
 

@@ -353,6 +353,29 @@ def test_mutual_pairs_split_workloads(k, tile):
     assert np.array_equal(H(outs[0][0]), H(outs[1][0])) and np.array_equal(H(outs[0][1]), H(outs[1][1]))
 
 
+@pytest.mark.parametrize("n", [8192, 9990, 10240, 13056])
+def test_mutual_pairs_split_last_round(n):
+    """Each pair once, shape (4, 4), at sizes whose last round of range pairs
+    is split into halves (one to three super-diagonals of split pairs, their
+    reactions in extra slots, the unused extra slots zero-filled by the
+    diagonal workgroups): FP64 and split accelerations against the oracle,
+    and 30 steps bitwise equal to 15 + 15."""
+    s = S.solar_system(41 + n, n - 31, n_major=30)
+    ref = oracle.accel(s.pos, s.mass, s.G)
+    m = T(s.mass)
+    for precision, tol in (("fp64", 1e-13), ("split", 2e-12)):
+        nb.set_tile(0, precision, n, 4, 4, 1, 5)
+        e = rel(H(nb.accel(T(s.pos), m, s.G, precision=precision)), ref)
+        log(f"mutual split round {precision} n={n}: rel {e:.2e}")
+        assert e <= tol
+        p1, v1 = T(s.pos), T(s.vel)
+        nb.verlet_run(p1, v1, m, s.G, 0.1, 30, precision=precision)
+        p2, v2 = T(s.pos), T(s.vel)
+        nb.verlet_run(p2, v2, m, s.G, 0.1, 15, precision=precision)
+        nb.verlet_run(p2, v2, m, s.G, 0.1, 15, precision=precision)
+        assert np.array_equal(H(p1), H(p2)) and np.array_equal(H(v1), H(v2))
+
+
 def test_mutual_pairs_rejected_where_unsupported():
     for tile in MUTUAL:   # beyond 131,072 bodies (512 ranges of partials)
         for precision in ("fp64", "split"):
