@@ -192,8 +192,12 @@ int32_t nbody_get_flags(void* workspace, void* stream, int32_t clear, int32_t* f
  * partial per range of 256 bodies and is accepted for n <= 131,072 (the
  * workspace of nbody_accel, nbody_verlet_run, nbody_rk4_run and
  * nbody_verlet_adjoint holds ceil(n / 256) partial slots up to that size:
- * 1.6 GB at n = 131,072).  Results stay bitwise repeatable.  The heuristic
- * picks (4, 4) from n = 4,300 (FP64) or 8,500 (split) up to n = 131,072. */
+ * 1.6 GB at n = 131,072).  With (4, 4), when the range pairs past the last
+ * whole round of 256 workgroups are few (at most 128, of at most 4,096
+ * pairs), each of them runs as two half-size workgroups and a few extra
+ * slots take the second halves' reactions (44 slots at n = 10,425).  Results
+ * stay bitwise repeatable.  The heuristic picks (4, 4) from n = 4,300 (FP64)
+ * or 8,500 (split) up to n = 131,072. */
 typedef struct {
     int32_t targets_per_lane;
     int32_t waves;
