@@ -92,7 +92,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the force pass would "
+        print("bench.py measures one GPU: the library has no multi-GPU path (the force pass would "
               "shard by targets with a per-step all-gather of positions). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
