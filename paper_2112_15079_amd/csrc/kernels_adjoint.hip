@@ -124,10 +124,10 @@ __global__ __launch_bounds__(64 * W) void k_vjp(const double* __restrict__ pos,
     for (int t = 0; t < T; ++t) {
         const int64_t p = tb0 + (int64_t)t * NT + tid;
         if (p < n) {
-            pc[p] = G * ox[t];
-            pc[n + p] = G * oy[t];
-            pc[2 * n + p] = G * oz[t];
-            pc[3 * n + p] = -G * og[t];
+            __builtin_nontemporal_store(G * ox[t], &pc[p]);
+            __builtin_nontemporal_store(G * oy[t], &pc[n + p]);
+            __builtin_nontemporal_store(G * oz[t], &pc[2 * n + p]);
+            __builtin_nontemporal_store(-G * og[t], &pc[3 * n + p]);
         }
     }
 }
@@ -234,10 +234,10 @@ __global__ __launch_bounds__(64 * W) void k_vjp_s(const double* __restrict__ pos
     for (int t = 0; t < T; ++t) {
         const int64_t p = tb0 + (int64_t)t * NT + tid;
         if (p < n) {
-            pc[p] = gc * ox[t];
-            pc[n + p] = gc * oy[t];
-            pc[2 * n + p] = gc * oz[t];
-            pc[3 * n + p] = -gc * og[t];
+            __builtin_nontemporal_store(gc * ox[t], &pc[p]);
+            __builtin_nontemporal_store(gc * oy[t], &pc[n + p]);
+            __builtin_nontemporal_store(gc * oz[t], &pc[2 * n + p]);
+            __builtin_nontemporal_store(-gc * og[t], &pc[3 * n + p]);
         }
     }
 }

@@ -220,9 +220,9 @@ __device__ __forceinline__ void force_block(const double* __restrict__ pos,
                 vy += (double)k.sy[t] - (double)k.cy[t];
                 vz += (double)k.sz[t] - (double)k.cz[t];
             }
-            part_c[p] = vx;
-            part_c[stride + p] = vy;
-            part_c[2 * stride + p] = vz;
+            __builtin_nontemporal_store(vx, &part_c[p]);
+            __builtin_nontemporal_store(vy, &part_c[stride + p]);
+            __builtin_nontemporal_store(vz, &part_c[2 * stride + p]);
         }
     }
 }
@@ -430,7 +430,7 @@ struct PartStore {
     int64_t stride;
     __device__ __forceinline__ void operator()(int comp, int64_t p, double a) const
     {
-        part_c[comp * stride + p] = a;
+        __builtin_nontemporal_store(a, &part_c[comp * stride + p]);
     }
 };
 

@@ -441,18 +441,18 @@ __device__ __forceinline__ void mutual_half_body(const double* __restrict__ pos,
             const int64_t i = (int64_t)(I0 + t) * 64 + lane;
             if (i < n) {
                 double* pt = part + (int64_t)r * plane;
-                pt[i] = ax[t];
-                pt[n + i] = ay[t];
-                pt[2 * n + i] = az[t];
+                __builtin_nontemporal_store(ax[t], &pt[i]);
+                __builtin_nontemporal_store(ay[t], &pt[n + i]);
+                __builtin_nontemporal_store(az[t], &pt[2 * n + i]);
             }
         }
     }
     const int64_t j = (int64_t)J * 64 + lane;
     if (j < n) {
         double* ps = part + (int64_t)(half == 0 ? g : xslot) * plane;
-        ps[j] = racc[w][0][lane];
-        ps[n + j] = racc[w][1][lane];
-        ps[2 * n + j] = racc[w][2][lane];
+        __builtin_nontemporal_store(racc[w][0][lane], &ps[j]);
+        __builtin_nontemporal_store(racc[w][1][lane], &ps[n + j]);
+        __builtin_nontemporal_store(racc[w][2][lane], &ps[2 * n + j]);
     }
 }
 
@@ -579,9 +579,9 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
                 const int64_t i = (int64_t)(I0 + t) * 64 + lane;
                 if (i < n) {
                     double* pt = part + (int64_t)r * plane;
-                    pt[i] = ax[t];
-                    pt[stride + i] = ay[t];
-                    pt[2 * stride + i] = az[t];
+                    __builtin_nontemporal_store(ax[t], &pt[i]);
+                    __builtin_nontemporal_store(ay[t], &pt[stride + i]);
+                    __builtin_nontemporal_store(az[t], &pt[2 * stride + i]);
                 }
             }
         }
@@ -589,9 +589,9 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
             const int64_t j = (int64_t)(J0 + jb) * 64 + lane;
             if (j < n) {
                 double* ps = part + (int64_t)g * plane;
-                ps[j] = racc[jb][0][lane];
-                ps[stride + j] = racc[jb][1][lane];
-                ps[2 * stride + j] = racc[jb][2][lane];
+                __builtin_nontemporal_store(racc[jb][0][lane], &ps[j]);
+                __builtin_nontemporal_store(racc[jb][1][lane], &ps[stride + j]);
+                __builtin_nontemporal_store(racc[jb][2][lane], &ps[2 * stride + j]);
             }
         }
     } else if (h == 0) {
@@ -603,16 +603,16 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
             const int jb = set * KMT + t;
             if (i < n) {
                 double* pt = part + (int64_t)g * plane;
-                pt[i] = ax[t] + racc[jb][0][lane];
-                pt[stride + i] = ay[t] + racc[jb][1][lane];
-                pt[2 * stride + i] = az[t] + racc[jb][2][lane];
+                __builtin_nontemporal_store(ax[t] + racc[jb][0][lane], &pt[i]);
+                __builtin_nontemporal_store(ay[t] + racc[jb][1][lane], &pt[stride + i]);
+                __builtin_nontemporal_store(az[t] + racc[jb][2][lane], &pt[2 * stride + i]);
                 // extra slot R + d - 1 is written by pair (g - d, g) if split
                 for (int d = 1; d <= tl.D; ++d) {
                     if (g >= d && (d < tl.D || g - d < tl.kD)) continue;
                     double* pz = part + (int64_t)(tl.R + d - 1) * plane;
-                    pz[i] = 0.0;
-                    pz[stride + i] = 0.0;
-                    pz[2 * stride + i] = 0.0;
+                    __builtin_nontemporal_store(0.0, &pz[i]);
+                    __builtin_nontemporal_store(0.0, &pz[stride + i]);
+                    __builtin_nontemporal_store(0.0, &pz[2 * stride + i]);
                 }
             }
         }
