@@ -191,7 +191,8 @@ int32_t nbody_get_flags(void* workspace, void* stream, int32_t clear, int32_t* f
  * pair of a target block holding a heavy body in FP64.  The pass writes one
  * partial per range of 256 bodies and is accepted for n <= 131,072 (the
  * workspace of nbody_accel, nbody_verlet_run, nbody_rk4_run and
- * nbody_verlet_adjoint holds ceil(n / 256) partial slots up to that size:
+ * nbody_verlet_adjoint holds ceil(n / 256) partial slots, or a few more
+ * for a split last round (below), up to that size:
  * 1.6 GB at n = 131,072).  With (4, 4), when the range pairs past the last
  * whole round of 256 workgroups are few (at most 128, of at most 4,096
  * pairs), each of them runs as two half-size workgroups and a few extra

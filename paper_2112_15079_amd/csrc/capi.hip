@@ -94,8 +94,8 @@ constexpr int64_t kMutualDefault = 4300;
 constexpr int64_t kMutualSplitDefault = 8500;
 
 // The each-pair-once pass serves single systems (FP64 or split) of up to
-// kMutualMaxN bodies: one partial per range of 256 bodies, 512 slots
-// (1.6 GB of partials) at the largest.
+// kMutualMaxN bodies: one partial per range of 256 bodies (plus a few for a
+// split last round), 512 slots (1.6 GB of partials) at the largest.
 constexpr int64_t kMutualMaxN = 131072;
 
 bool mutual_fits(int kind, int prec, int64_t n)

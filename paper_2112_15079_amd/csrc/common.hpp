@@ -78,9 +78,10 @@ hipError_t launch_force_batched(int precision, const Tile& tile, const double* p
                                 const BatchUnit* units, int64_t num_units, const int64_t* nmaj,
                                 int grid, double* part, hipStream_t s);
 
-// ----- each pair once (variant 5, FP64) -----------------------------------------
+// ----- each pair once (variant 5, FP64 or split) -------------------------------
 // Ranges of 4 blocks of 64 bodies; the pass writes one partial per range and
-// body (slot order = range order), summed by the ordinary step epilogue.
+// body (slot order = range order), plus the extra slots of a split last round,
+// summed by the ordinary step epilogue.
 int mutual_ranges(int64_t n);
 // Partial slots of a single system's pass: the ranges, plus the extra slots
 // of the split last round (shape (4, 4) only).
