@@ -95,6 +95,23 @@ def test_adjoint_transpose_pass_tiles(vtile, n_small):
     nb.reset_caches()
 
 
+def test_adjoint_autotune_then_parity():
+    """The autotuner over the transpose-Jacobian pass's tiles (LDS-staged and
+    scalar-operand sources) keeps a supported tile for the size class, and the
+    adjoint run with it matches the oracle."""
+    nb.reset_caches()
+    s = S.solar_system(47, 300, n_major=19)
+    tile, ms = nb.autotune(T(s.pos), T(s.mass), s.G, kind=1)
+    print(f"autotune adjoint pass n={s.n}: {tile} {ms:.4f} ms", flush=True)
+    assert tile == nb.get_tile(1, "fp64", s.n) and tile["variant"] in (0, 1) and ms > 0
+    rng = np.random.default_rng(9)
+    lr, lv = rng.normal(size=(3, s.n)), rng.normal(size=(3, s.n)) * 10
+    gr, gv, gm = oracle.adjoint(s.pos, s.vel, s.mass, s.G, 0.1, 30, lr, lv)
+    Gr, Gv, Gm, _, _ = nb.verlet_adjoint(T(s.pos), T(s.vel), T(s.mass), s.G, 0.1, 30, 7, T(lr), T(lv))
+    assert nrel(H(Gr), gr) <= 1e-10 and nrel(H(Gv), gv) <= 1e-10 and nrel(H(Gm), gm) <= 1e-10
+    nb.reset_caches()
+
+
 def test_adjoint_full_size_prefix_matches_oracle():
     """The 2,079-body adjoint workload at full size in the benchmark's launch
     configuration (default tiles, checkpoints every 100 steps, ragged last
