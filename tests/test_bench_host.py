@@ -1,0 +1,31 @@
+"""bench.py's host-side contract, without a GPU: one GPU only, the metric's
+name for a system size, and the traffic figure taken from the committed
+rocprofv3 summary only when it matches the tile being measured."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_metric_names_the_system_size():
+    assert bench.metric_at(10425).startswith("pair interactions/s + steps/s at N=10,425:")
+    assert "N=131,072" in bench.metric_at(131072)
+
+
+def test_traffic_only_for_the_profiled_tile():
+    tile = {"targets_per_lane": 4, "waves": 4, "chunks": 1, "variant": 5}
+    t = bench.read_traffic("force_fp64_n10425", tile)
+    assert t is not None and t > 32 * 10425        # at least the source reads
+    assert bench.read_traffic("force_fp64_n10425", dict(tile, variant=1)) is None
+    assert bench.read_traffic("no_such_profile", tile) is None
