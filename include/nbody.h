@@ -194,7 +194,7 @@ int32_t nbody_get_flags(void* workspace, void* stream, int32_t clear, int32_t* f
  * nbody_verlet_adjoint holds ceil(n / 256) partial slots, or a few more
  * for a split last round (below), up to that size:
  * 1.6 GB at n = 131,072).  With (4, 4), when the range pairs past the last
- * whole round of 256 workgroups are few (at most 128, of at most 4,096
+ * whole round of 256 workgroups are few (at most 128, of at most 16,384
  * pairs), each of them runs as two half-size workgroups and a few extra
  * slots take the second halves' reactions (44 slots at n = 10,425).  Results
  * stay bitwise repeatable.  The heuristic picks (4, 4) from n = 4,300 (FP64)

@@ -666,7 +666,7 @@ static MutualTail mutual_tail(int64_t n, int tpl, int waves)
     t.kD = 0;
     // split only the pairs past the last whole round, when their halves fit
     // in one round and they are off the diagonal
-    if (tpl != 4 || waves != 4 || U > 16 * kMutualCUs || rem == 0 || 2 * rem > kMutualCUs ||
+    if (tpl != 4 || waves != 4 || U > 64 * kMutualCUs || rem == 0 || 2 * rem > kMutualCUs ||
         rem > U - t.R)
         return t;
     int64_t left = rem;

@@ -54,7 +54,7 @@ static int check(int64_t n, int tpl, int waves, bool verbose)
 int main()
 {
     int bad = 0, cnt = 0;
-    for (int64_t n : {1, 100, 4096, 5632, 8192, 9728, 9984, 10240, 10425, 11520, 13056, 16384, 23000, 131072}) bad |= check(n, 4, 4, true);
+    for (int64_t n : {1, 100, 4096, 5632, 8192, 9728, 9984, 10240, 10425, 11520, 13056, 16384, 23000, 30000, 40000, 46000, 46100, 131072}) bad |= check(n, 4, 4, true);
     for (int64_t n = 1; n <= 30000 && !bad; n += (n < 3000 ? 7 : 13)) { bad |= check(n, 4, 4, false); bad |= check(n, 2, 4, false); ++cnt; }
     printf("%s (%d sizes)\n", bad ? "FAIL" : "ok", cnt);
     return bad;
