@@ -353,7 +353,7 @@ def test_mutual_pairs_split_workloads(k, tile):
     assert np.array_equal(H(outs[0][0]), H(outs[1][0])) and np.array_equal(H(outs[0][1]), H(outs[1][1]))
 
 
-@pytest.mark.parametrize("n", [8192, 9990, 10240, 13056, 30000])
+@pytest.mark.parametrize("n", [8192, 9990, 10240, 13056, 30000, 45500])
 def test_mutual_pairs_split_last_round(n):
     """Each pair once, shape (4, 4), at sizes whose last round of range pairs
     is split into halves (one to three super-diagonals of split pairs, their
