@@ -490,6 +490,25 @@ def test_split_all_major_is_one_newton_step():
     assert e <= 2e-12
 
 
+def test_many_partials_step_bitwise():
+    """65,600 bodies: the each-pair-once pass writes 257 partial slots, which
+    the step epilogue adds with one thread per element.  Sampled
+    accelerations against the oracle, and 4 steps bitwise equal to 2 + 2."""
+    s = S.solar_system(65, 65600 - 31, n_major=30)
+    m = T(s.mass)
+    idx = np.unique(np.concatenate([[0, 1, 30, 31, s.n - 1],
+                                    np.random.default_rng(2).choice(s.n, 40, replace=False)]))
+    e = rel(H(nb.accel(T(s.pos), m, s.G))[:, idx], oracle.accel_targets(s.pos, s.mass, s.G, idx))
+    log(f"n={s.n} sampled accel rel={e:.2e}")
+    assert e <= 1e-13
+    p1, v1 = T(s.pos), T(s.vel)
+    nb.verlet_run(p1, v1, m, s.G, 0.1, 4)
+    p2, v2 = T(s.pos), T(s.vel)
+    nb.verlet_run(p2, v2, m, s.G, 0.1, 2)
+    nb.verlet_run(p2, v2, m, s.G, 0.1, 2)
+    assert np.array_equal(H(p1), H(p2)) and np.array_equal(H(v1), H(v2))
+
+
 def test_split_131072_sampled_error():
     s = S.config(2)
     rng = np.random.default_rng(1)
