@@ -11,7 +11,7 @@ using namespace pm;
 
 constexpr int kBlock = 256;
 
-// Sum the chunk partials of a_p in ascending chunk order, then apply the
+// Sum the chunk partials of a_p in a fixed order (below), then apply the
 // half kicks and the drift:
 //   kClose: v += dt/2 a                         (v_{i+1}, end of step i)
 //   kOpen:  v += dt/2 a;  r_out = r_in + dt v   (v_{i+3/2}, r_{i+2})
