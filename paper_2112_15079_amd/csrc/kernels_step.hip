@@ -398,12 +398,12 @@ hipError_t launch_step(const double* part, int chunks, const int8_t* body_chunks
                        double dt, int mode, uint32_t* flags, hipStream_t s)
 {
     // several threads per element when there are many chunk partials to add
-    // (the ensemble's per-body chunk counts are at most 16); with hundreds of
-    // partials (the each-pair-once pass on large systems) one thread per
-    // element again, so that each load of a wavefront reads 512 contiguous
-    // bytes of one partial plane
+    // (the ensemble's per-body chunk counts are at most 16); with a hundred
+    // partials or more (the each-pair-once pass on large systems) one thread
+    // per element again, so that each load of a wavefront reads 512
+    // contiguous bytes of one partial plane
     const int max_chunks = body_chunks ? 16 : chunks;
-    if (max_chunks >= 256)
+    if (max_chunks >= 96)
         hipLaunchKernelGGL(k_step<1>, dim3(blocks_for(3 * n, kBlock)), dim3(kBlock), 0, s, part,
                            chunks, body_chunks, n, vel, pos_in, pos_out, acc, 0.5 * dt, dt, mode,
                            flags);
