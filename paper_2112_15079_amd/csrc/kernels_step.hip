@@ -398,7 +398,7 @@ hipError_t launch_step(const double* part, int chunks, const int8_t* body_chunks
                        double dt, int mode, uint32_t* flags, hipStream_t s)
 {
     // several threads per element when there are many chunk partials to add
-    // (the ensemble's per-body chunk counts are at most 16); with a hundred
+    // (an ensemble's per-body counts, at most 40, take this path); with a hundred
     // partials or more (the each-pair-once pass on large systems) one thread
     // per element again, so that each load of a wavefront reads 512
     // contiguous bytes of one partial plane
