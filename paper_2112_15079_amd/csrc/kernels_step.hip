@@ -397,17 +397,11 @@ hipError_t launch_step(const double* part, int chunks, const int8_t* body_chunks
                        double* vel, const double* pos_in, double* pos_out, double* acc,
                        double dt, int mode, uint32_t* flags, hipStream_t s)
 {
-    // several threads per element when there are many chunk partials to add
-    // (an ensemble's per-body counts, at most 40, take this path); with a hundred
-    // partials or more (the each-pair-once pass on large systems) one thread
-    // per element again, so that each load of a wavefront reads 512
-    // contiguous bytes of one partial plane
-    const int max_chunks = body_chunks ? 16 : chunks;
-    if (max_chunks >= 96)
-        hipLaunchKernelGGL(k_step<1>, dim3(blocks_for(3 * n, kBlock)), dim3(kBlock), 0, s, part,
-                           chunks, body_chunks, n, vel, pos_in, pos_out, acc, 0.5 * dt, dt, mode,
-                           flags);
-    else if (max_chunks >= 16)
+    // four threads per element for 16 to 95 partials of a single system; one
+    // below that, from 96 partials (the each-pair-once pass on large systems)
+    // and for an ensemble's per-body counts, where each load of a wavefront
+    // then reads 512 contiguous bytes of one partial plane (measured faster)
+    if (!body_chunks && chunks >= 16 && chunks < 96)
         hipLaunchKernelGGL(k_step<4>, dim3(blocks_for(12 * n, kBlock)), dim3(kBlock), 0, s, part,
                            chunks, body_chunks, n, vel, pos_in, pos_out, acc, 0.5 * dt, dt, mode,
                            flags);
