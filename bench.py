@@ -13,6 +13,7 @@ CPU oracle's rate on this host.
     python bench.py --workload {solar-131,solar-131072,ensemble,adjoint}
     python bench.py --workload dt-scan    # accuracy against the step size (Sec. 4)
     python bench.py --workload n-scan     # throughput against N, GPU and oracle (Sec. 5)
+    python bench.py --workload force      # force passes only (for counter profiles)
 """
 from __future__ import annotations
 
@@ -31,11 +32,14 @@ def metric_at(n):
     """The headline metric's name for a single system of n bodies."""
     return f"pair interactions/s + steps/s at N={n:,}: FP64 vs split-precision at fixed ΔE/E"
 FP64_PEAK_TFLOPS = 78.6          # MI355X vector FP64, 256 CU x 64 lanes x 2 x 2.4 GHz
+FP32_PEAK_TFLOPS = 157.3         # MI355X vector FP32 (packed)
 HBM_PEAK_GBS = 8000.0
-FLOPS_PER_PAIR = 20              # algorithmic convention for one pair interaction
-# each unordered pair once (Newton's third law): the pair's 20 flops serve the
-# target, and the reaction on the source adds 7 (the source-side mass scale
-# and three fused multiply-adds)
+# algorithmic work of one force pass: 20 flops per ordered pair interaction,
+# N (N - 1) of them, whichever kernel evaluates them
+FLOPS_PER_PAIR = 20
+# the each-pair-once kernel's own arithmetic per unordered pair: the pair's 20
+# flops serve the target, and the reaction on the source adds 7 (the
+# source-side mass scale and three fused multiply-adds)
 FLOPS_PER_MUTUAL_PAIR = 27
 
 
@@ -50,11 +54,17 @@ def parse():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="solar-10425",
                     choices=["solar-10425", "solar-131", "solar-131072", "ensemble", "adjoint",
-                             "dt-scan", "n-scan", "copy"])
+                             "dt-scan", "n-scan", "copy", "force"])
     ap.add_argument("--tune", action="store_true",
                     help="single-system workloads: autotune the force tiles first (the default "
                          "is the library's sweep-derived heuristic; the ensemble always autotunes)")
+    ap.add_argument("--settle-ms", type=float, default=60.0,
+                    help="untimed force passes (about this many ms of GPU work) right before "
+                         "each timed run, so that the GPU's clock has reached its sustained "
+                         "level under load (0: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra-legs", action="store_true",
+                    help="solar-10425: skip the paper-shaped run and the RK4 leg (counter passes)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU time budget of the oracle sample")
     ap.add_argument("--fd-coords", type=int, default=64, help="adjoint workload: FD coordinates")
@@ -70,11 +80,10 @@ def tile_str(t):
     return f"{t['targets_per_lane']},{t['waves']},{t['chunks']},{t['variant']}"
 
 
-def read_traffic(kernel_key, tile):
-    """HBM bytes per launch from a committed rocprofv3 --pmc summary
-    (profiles/<kernel_key>_traffic.txt, lines 'key: value'), if it was taken
-    with this tile shape; None otherwise."""
-    path = os.path.join(ROOT, "profiles", f"{kernel_key}_traffic.txt")
+def read_profile(name, tile):
+    """The 'key: value' lines of a committed rocprofv3 summary
+    (profiles/<name>.txt) if it was taken with this tile shape, else None."""
+    path = os.path.join(ROOT, "profiles", f"{name}.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -82,12 +91,44 @@ def read_traffic(kernel_key, tile):
         if ":" in line and not line.lstrip().startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("tile") != tile_str(tile):
-        return None
+    return vals if vals.get("tile") == tile_str(tile) else None
+
+
+def read_traffic(kernel_key, tile):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary
+    (profiles/<kernel_key>_traffic.txt), if it was taken with this tile
+    shape; None otherwise."""
+    vals = read_profile(f"{kernel_key}_traffic", tile)
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals["hbm_bytes_per_launch"]) if vals else None
     except (KeyError, ValueError):
         return None
+
+
+def counter_fractions(kernel_key, tile, ms):
+    """FP64 and FP32 vector FLOP/s of the force kernel as fractions of the
+    chip's peaks: counter flops per launch (rocprofv3 --pmc, FLOPs =
+    64 (ADD + MUL + TRANS + 2 FMA) per precision) from the committed summary
+    profiles/<kernel_key>_counters.txt taken with this tile, over the launch
+    time measured now (ms).  None if no such summary exists."""
+    vals = read_profile(f"{kernel_key}_counters", tile)
+    if not vals:
+        return None
+    try:
+        f64 = float(vals["fp64_flops_per_launch"])
+        f32 = float(vals["fp32_flops_per_launch"])
+    except (KeyError, ValueError):
+        return None
+    s = ms * 1e-3
+    out = {"counter_frac_fp64": round(f64 / s / 1e12 / FP64_PEAK_TFLOPS, 4),
+           "counter_frac_fp32": round(f32 / s / 1e12 / FP32_PEAK_TFLOPS, 4)}
+    for k in ("sclk_ghz", "valu_busy", "valu_issue_frac_of_sclk"):
+        if k in vals:
+            try:
+                out[k] = float(vals[k])
+            except ValueError:
+                pass
+    return out
 
 
 def main():
@@ -120,6 +161,8 @@ def main():
         return bench_dt_scan(args, S, nb, torch, np, dev)
     if args.workload == "n-scan":
         return bench_n_scan(args, S, nb, torch, np, dev)
+    if args.workload == "force":
+        return bench_force(args, S, nb, torch, np, dev)
     k = {"solar-131": 0, "solar-10425": 1, "solar-131072": 2}[args.workload]
     return bench_single(args, k, S, nb, torch, np, dev)
 
@@ -128,10 +171,23 @@ def _t(a, torch, dev):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
 
 
+def settle_clock(nb, pos, m, G, prec, ms):
+    """Untimed force passes on `pos` for about `ms` milliseconds of GPU work.
+    The GPU raises its clock over the first tens of milliseconds of sustained
+    load (a trace of one 1000-step run at N = 10,425 shows the force pass
+    falling from 54 to 46.7 us over its first ~30 ms), so a timed window of a
+    few steps that starts from an idle GPU measures that ramp rather than the
+    kernels' sustained rate.  Nothing here changes the state of the run."""
+    if ms <= 0:
+        return
+    per = nb.time_force(pos, m, G, prec, reps=3)
+    nb.time_force(pos, m, G, prec, reps=max(1, int(ms / max(per, 1e-3))))
+
+
 def bench_single(args, k, S, nb, torch, np_, dev):
     s = S.config(k)
     n, G, dt = s.n, s.G, s.dt
-    K = args.steps if args.steps is not None else {0: 3650, 1: 10000, 2: 200}[k]
+    K = args.steps if args.steps is not None else {0: 3650, 1: 10000, 2: 1000}[k]
     W = args.warmup if args.warmup is not None else {0: 365, 1: 200, 2: 10}[k]
     log(f"workload {s.name}: n={n}, dt={dt}, steps={K}, warmup={W}")
     pos0, vel0, m = _t(s.pos, torch, dev), _t(s.vel, torch, dev), _t(s.mass, torch, dev)
@@ -147,13 +203,14 @@ def bench_single(args, k, S, nb, torch, np_, dev):
 
     E0 = nb.energy(pos0, vel0, m, G)[2].item()
     results = {}
-    for prec in ("fp64", "split"):
+    for prec in ("fp64", "split", "compensated"):
         # the same buffers for the warm-up and the timed run: captured step
         # graphs are keyed by the buffers they run on
         p, v = pos0.clone(), vel0.clone()
         nb.verlet_run(p, v, m, G, dt, W, precision=prec)        # warm-up (graphs, caches)
         p.copy_(pos0)
         v.copy_(vel0)
+        settle_clock(nb, pos0, m, G, prec, args.settle_ms)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -194,32 +251,26 @@ def bench_single(args, k, S, nb, torch, np_, dev):
         return float(np.max(np.linalg.norm(a - a_ref, axis=0) / np.linalg.norm(a_ref, axis=0)))
 
     err64, errsp = acc_err("fp64"), acc_err("split")
+    rcp = results["compensated"]
+    vcp, spscp = rate(rcp)
+    mscp = nb.time_force(pos0, m, G, "compensated", reps=max(3, (args.force_reps or 20) // 2))
+    comp = {"pairs_per_s": vcp, "steps_per_s": spscp, "ms_per_step": 1e3 * rcp["wall"] / K,
+            "dE_over_E": (rcp["E"] - E0) / abs(E0),
+            "E_minus_E_fp64_over_E0": (rcp["E"] - r64["E"]) / abs(E0),
+            "accel_max_rel_err_vs_oracle": acc_err("compensated"),
+            "speedup_vs_fp64": vcp / v64, "ms_per_launch": round(mscp, 5),
+            "tile": nb.get_tile(0, "compensated", n), "gpu_event_s": rcp["gpu"],
+            "form": "split as specified: FP64 d and r^2, FP32 rsqrt + one FP64 Newton step, "
+                    "light terms in FP32 Kahan sums"}
 
     # force-kernel timing for the roofline (HIP events around the force kernels only)
     reps = args.force_reps or max(20, min(2000, int(2e11 / pairs)))
     ms64 = nb.time_force(pos0, m, G, "fp64", reps=reps)
     mssp = nb.time_force(pos0, m, G, "split", reps=reps)
     t64 = tiles["fp64"]
-    mutual = t64["variant"] == 5
-    flops = FLOPS_PER_MUTUAL_PAIR * pairs // 2 if mutual else FLOPS_PER_PAIR * pairs
-    achieved = flops / (ms64 * 1e-3) / 1e12
-    kname = ({0: "k_force (LDS tiles)", 1: "k_force_s (scalar operands)",
-              2: "k_force_s (shared targets)", 3: "k_run_small (one workgroup)",
-              4: "k_step_fused (force pass and step)",
-              5: "k_force_mutual (each pair once)"}[t64["variant"]]
-             + f" FP64, tile {tile_str(t64)}")
-    roof = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3),
-            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-            "traffic": read_traffic(f"force_fp64_n{n}", t64),
-            "ms_per_launch": round(ms64, 5), "flops_per_launch": flops,
-            "split_ms_per_launch": round(mssp, 5)}
-    if mutual:
-        # the same launch in the one-way convention (20 flops per ordered pair)
-        eq = FLOPS_PER_PAIR * pairs / (ms64 * 1e-3) / 1e12
-        roof["ordered_pair_equivalent"] = {"achieved": round(eq, 3),
-                                           "frac": round(eq / FP64_PEAK_TFLOPS, 4)}
-    log(f"force pass: fp64 {ms64:.4f} ms ({achieved:.2f} TFLOP/s alg.), split {mssp:.4f} ms")
+    roof = roofline(n, t64, ms64, mssp)
+    log(f"force pass: fp64 {ms64:.4f} ms ({roof['achieved']:.2f} TFLOP/s alg.), "
+        f"split {mssp:.4f} ms")
 
     line = {
         "metric": metric_at(n),
@@ -228,6 +279,7 @@ def bench_single(args, k, S, nb, torch, np_, dev):
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
+        "settle_ms": args.settle_ms,
         "ms_per_step": 1e3 * r64["wall"] / K,
         "higher_is_better": True,
         "scaling": "weak",
@@ -246,14 +298,66 @@ def bench_single(args, k, S, nb, torch, np_, dev):
                   "E_split_minus_E_fp64_over_E0": (rsp["E"] - r64["E"]) / abs(E0),
                   "accel_max_rel_err_vs_oracle": errsp, "speedup_vs_fp64": vsp / v64,
                   "tile": tiles["split"], "gpu_event_s": rsp["gpu"]},
+        "split_compensated": comp,
         "roofline": roof,
     }
-    if k == 1:
+    if k == 1 and not args.no_extra_legs:
         line["paper_run"] = paper_run(nb, torch, pos0, vel0, m, G, dt)
         line["rk4"] = rk4_rate(nb, torch, pos0, vel0, m, G, dt, n)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds, k)
     print(json.dumps(line), flush=True)
+
+
+KERNEL_NAMES = {0: "k_force (LDS tiles)", 1: "k_force_s (scalar operands)",
+                2: "k_force_s (shared targets)", 3: "k_run_small (one workgroup)",
+                4: "k_step_fused (force pass and step)", 5: "k_force_mutual (each pair once)"}
+
+
+def roofline(n, tile, ms64, mssp):
+    """Roofline object of the FP64 force kernel: algorithmic flops per launch
+    (20 N (N - 1)) over its measured launch time against the FP64 vector peak;
+    for the each-pair-once kernel also its own arithmetic (27 flops per
+    unordered pair); counter fractions and HBM traffic from committed
+    rocprofv3 summaries taken with the same tile."""
+    pairs = n * (n - 1)
+    flops = FLOPS_PER_PAIR * pairs
+    achieved = flops / (ms64 * 1e-3) / 1e12
+    roof = {"bound": "alu",
+            "kernel": KERNEL_NAMES[tile["variant"]] + f" FP64, tile {tile_str(tile)}",
+            "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+            "traffic": read_traffic(f"force_fp64_n{n}", tile),
+            "ms_per_launch": round(ms64, 5), "flops_per_launch": flops,
+            "split_ms_per_launch": round(mssp, 5)}
+    if tile["variant"] == 5:
+        own = FLOPS_PER_MUTUAL_PAIR * pairs // 2
+        a = own / (ms64 * 1e-3) / 1e12
+        roof["own_arithmetic"] = {"flops_per_launch": own, "achieved": round(a, 3),
+                                  "frac": round(a / FP64_PEAK_TFLOPS, 4)}
+    cf = counter_fractions(f"force_fp64_n{n}", tile, ms64)
+    if cf:
+        roof.update(cf)
+    return roof
+
+
+def bench_force(args, S, nb, torch, np_, dev):
+    """The force passes alone on the 10,425-body system (no step loop, no
+    graphs): the command the counter profiles are taken with."""
+    s = S.config(1)
+    n, G = s.n, s.G
+    pos0, m = _t(s.pos, torch, dev), _t(s.mass, torch, dev)
+    reps = args.force_reps or 200
+    out = {"metric": "force pass time", "unit": "ms", "n": n, "reps": reps, "n_gpus": 1,
+           "dtype": "f64", "data": "synthetic"}
+    for prec in ("fp64", "split", "compensated"):
+        settle_clock(nb, pos0, m, G, prec, args.settle_ms)
+        out[prec] = {"ms_per_launch": nb.time_force(pos0, m, G, prec, reps=reps),
+                     "tile": nb.get_tile(0, prec, n)}
+        log(f"force {prec}: {out[prec]['ms_per_launch']:.4f} ms per launch")
+    out["roofline"] = roofline(n, out["fp64"]["tile"], out["fp64"]["ms_per_launch"],
+                               out["split"]["ms_per_launch"])
+    print(json.dumps(out), flush=True)
 
 
 def rk4_rate(nb, torch, pos0, vel0, m, G, dt, n, steps=1000):

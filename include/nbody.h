@@ -61,8 +61,26 @@ typedef enum {
      * sources with mass >= small_mass; 1/|r|^3 from an FP32 reciprocal
      * square root refined by one FP64 Newton step for those sources;
      * sources lighter than small_mass are summed in FP32 with Kahan
-     * compensation. */
-    NBODY_SPLIT = 1
+     * compensation.  As run: where the each-pair-once pass (tile variant 5)
+     * runs, a pair of two light bodies is evaluated wholly in FP32 (FP32
+     * displacement, squared distance and reciprocal square root, no Newton
+     * step) and its terms summed in blocks of 16 in FP32, each block added
+     * to an FP64 sum; every other pair as in NBODY_FP64.  The one-way passes
+     * form light sources' terms in FP32 and add blocks of 16 to a Kahan sum.
+     * Faster than NBODY_FP64. */
+    NBODY_SPLIT = 1,
+    /* Split precision exactly as the split form is specified: FP64
+     * displacement, squared distance, kicks and drifts; for every pair
+     * 1/|r|^3 = y^3 with y the FP32 reciprocal square root of float(r^2)
+     * refined by one FP64 Newton step; terms of sources with mass >=
+     * small_mass accumulated in FP64, terms of lighter sources rounded to
+     * FP32 (float(G m y^3) * float(d)) and accumulated in FP32 with Kahan
+     * compensation (per workgroup of the each-pair-once pass, whose partial
+     * sums are then added in FP64).  Runs in the each-pair-once pass only:
+     * single systems of at most 131,072 bodies, ensembles of systems of at
+     * most 10,240; NBODY_EUNSUPPORTED beyond.  Slower than NBODY_FP64 (about
+     * twice the instructions per pair). */
+    NBODY_SPLIT_COMPENSATED = 2
 } nbody_precision;
 
 typedef enum {

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnbody.so")
 
 NBODY_OK, NBODY_EINVAL, NBODY_EUNSUPPORTED, NBODY_EWORKSPACE, NBODY_EHIP = range(5)
-NBODY_FP64, NBODY_SPLIT = 0, 1
+NBODY_FP64, NBODY_SPLIT, NBODY_SPLIT_COMPENSATED = 0, 1, 2
 OP_ACCEL, OP_RUN, OP_ADJOINT, OP_BATCHED, OP_ENERGY, OP_RK4 = range(6)
 
 EXPORTS = (

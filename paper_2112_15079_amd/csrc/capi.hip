@@ -139,6 +139,8 @@ Tile force_only_tile(int prec, int64_t n)
 
 Tile heuristic_tile(int kind, int prec, int64_t n)
 {
+    // the compensated split form runs in the each-pair-once pass only
+    if (prec == NBODY_SPLIT_COMPENSATED) return Tile{4, 4, 1, 5};
     if (kind == 2) return Tile{2, 1, kBatchChunkMax, 0};   // ensemble: per-system chunks
     if (kind == 0 && n <= kSmallDefault)
         return Tile{1, 16, (int)std::max<int64_t>(1, std::min<int64_t>(16, 1024 / n)), 3};
@@ -163,7 +165,8 @@ Tile pick_tile(int kind, int prec, int64_t n)
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_tiles.find(std::make_tuple(kind, prec, size_class(n)));
         if (it != g_tiles.end() && !(it->second.variant == 3 && n > kSmallMax) &&
-            !(it->second.variant == 5 && !mutual_fits(kind, prec, n))) {
+            !(it->second.variant == 5 && !mutual_fits(kind, prec, n)) &&
+            !(prec == NBODY_SPLIT_COMPENSATED && it->second.variant != 5)) {
             Tile t = it->second;
             t.chunks = std::min(t.chunks, chunk_cap(n));
             return t;
@@ -207,7 +210,7 @@ Layout layout(int op, int64_t n, int32_t ns, int64_t steps, int64_t K, int prec)
     L.part = a.take((size_t)cap * planes * n * d);
     L.alt = a.take(3 * n * d);
     L.gm = a.take(n * d);
-    if (prec == NBODY_SPLIT && op != NBODY_OP_ADJOINT && op != NBODY_OP_ENERGY) {
+    if (prec != NBODY_FP64 && op != NBODY_OP_ADJOINT && op != NBODY_OP_ENERGY) {
         L.perm = a.take(n * sizeof(int32_t));
         L.nmaj = a.take((size_t)ns * sizeof(int64_t));
         L.offs = a.take((size_t)(ns + 1) * sizeof(int64_t));
@@ -269,10 +272,21 @@ int check_common(const void* pos, const void* mass, int64_t n, double G)
 
 int check_prec(int32_t prec, double small_mass)
 {
-    if (prec != NBODY_FP64 && prec != NBODY_SPLIT)
+    if (prec != NBODY_FP64 && prec != NBODY_SPLIT && prec != NBODY_SPLIT_COMPENSATED)
         return fail(NBODY_EINVAL, "unknown precision %d", prec);
-    if (prec == NBODY_SPLIT && !(small_mass >= 0.0 && std::isfinite(small_mass)))
+    if (prec != NBODY_FP64 && !(small_mass >= 0.0 && std::isfinite(small_mass)))
         return fail(NBODY_EINVAL, "split threshold must be finite and >= 0");
+    return NBODY_OK;
+}
+
+// The compensated split form runs in the each-pair-once pass, which takes
+// single systems of up to kMutualMaxN bodies.
+int check_comp_size(int32_t prec, int64_t n)
+{
+    if (prec == NBODY_SPLIT_COMPENSATED && n > kMutualMaxN)
+        return fail(NBODY_EUNSUPPORTED,
+                    "the compensated split form takes at most %lld bodies (got %lld)",
+                    (long long)kMutualMaxN, (long long)n);
     return NBODY_OK;
 }
 
@@ -383,16 +397,16 @@ uint64_t bits(double x)
 
 uint64_t ptrbits(const void* p) { return (uint64_t)reinterpret_cast<uintptr_t>(p); }
 
-// Captures `body(stream)` once per key (plus the current device) and launches
-// the instantiated graph on `stream`.  body must only enqueue kernels.
+// The cached graph for key_in on the current device, captured from
+// `body(stream)` first if there is none.  body must only enqueue kernels.
+// Call with g_graph_mu held.
 template <typename F>
-int run_graph(const GraphKey& key_in, hipStream_t stream, F&& body)
+int find_or_capture(const GraphKey& key_in, F&& body, GraphEntry** out)
 {
     int dev = 0;
     NB_HIP(hipGetDevice(&dev));
     GraphKey key = key_in;
     key.v.push_back((uint64_t)dev);
-    std::lock_guard<std::mutex> lk(g_graph_mu);
     auto it = g_graphs.find(key);
     if (it == g_graphs.end()) {
         hipStream_t cs = nullptr;
@@ -426,7 +440,19 @@ int run_graph(const GraphKey& key_in, hipStream_t stream, F&& body)
         it = g_graphs.emplace(key, e).first;
     }
     it->second.used = ++g_graph_tick;
-    NB_HIP(hipGraphLaunch(it->second.exec, stream));
+    *out = &it->second;
+    return NBODY_OK;
+}
+
+// Captures `body` once per key (plus the current device) and launches the
+// instantiated graph on `stream`.
+template <typename F>
+int run_graph(const GraphKey& key, hipStream_t stream, F&& body)
+{
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    GraphEntry* e = nullptr;
+    NB_TRY(find_or_capture(key, body, &e));
+    NB_HIP(hipGraphLaunch(e->exec, stream));
     return NBODY_OK;
 }
 
@@ -492,35 +518,42 @@ int step_launch(const StepPlan& P, int64_t i, int64_t steps, hipStream_t s)
     return force_and_step(P, P.buf[i & 1], P.buf[(i + 1) & 1], mode, s);
 }
 
-constexpr int64_t kGraphSteps = 64;   // middle steps per captured graph (even)
+constexpr int64_t kGraphSteps = 64;   // middle launches per captured graph
+
+GraphKey steps_key(const StepPlan& P)
+{
+    GraphKey key;
+    key.v = {1, (uint64_t)P.prec, (uint64_t)P.tile.tpl, (uint64_t)P.tile.waves,
+             (uint64_t)P.tile.chunks, (uint64_t)P.tile.variant, (uint64_t)P.chunks, (uint64_t)P.n,
+             bits(P.G), bits(P.dt), ptrbits(P.mass), ptrbits(P.gm), ptrbits(P.vel),
+             ptrbits(P.buf[0]), ptrbits(P.buf[1]), ptrbits(P.part), ptrbits(P.flags),
+             ptrbits(P.nmaj), ptrbits(P.units), (uint64_t)P.num_units, (uint64_t)P.grid,
+             ptrbits(P.bchunks)};
+    return key;
+}
 
 // Launches 0..steps; r_0 must be in buf[0].  The final r_steps lands in
-// buf[steps & 1].  Middle launches are replayed from a captured graph.
+// buf[steps & 1].  With use_graph the middle launches (both half kicks and
+// the drift) run as replays of one captured graph of kGraphSteps launches,
+// each replay starting on an odd launch index (r_i in buf[1]); the first
+// launch, the last and the middle ones left over are enqueued directly.
+// (Once the GPU's clock has settled, direct launches cost no more GPU time
+// than graph replays for a short run; graphs save host time on long ones.)
 int run_steps(const StepPlan& P, int64_t steps, hipStream_t stream, bool use_graph)
 {
     if (steps <= 0) return NBODY_OK;
     NB_TRY(step_launch(P, 0, steps, stream));
     int64_t i = 1;
-    const int64_t middle = steps - 1;
-    if (use_graph && middle >= 2 * kGraphSteps) {
-        GraphKey key;
-        key.v = {1, (uint64_t)P.prec, (uint64_t)P.tile.tpl, (uint64_t)P.tile.waves,
-                 (uint64_t)P.tile.chunks, (uint64_t)P.tile.variant, (uint64_t)P.chunks, (uint64_t)P.n, bits(P.G), bits(P.dt),
-                 ptrbits(P.mass), ptrbits(P.vel), ptrbits(P.buf[0]), ptrbits(P.buf[1]),
-                 ptrbits(P.part), ptrbits(P.flags), ptrbits(P.nmaj), ptrbits(P.units),
-                 (uint64_t)P.num_units, (uint64_t)P.grid, ptrbits(P.bchunks)};
-        const int64_t reps = middle / kGraphSteps;
-        for (int64_t r = 0; r < reps; ++r) {
-            // every replay starts at an odd launch index (r_i in buf[1])
+    if (use_graph && steps > kGraphSteps) {
+        const GraphKey key = steps_key(P);
+        for (; i + kGraphSteps <= steps; i += kGraphSteps)   // launches i .. i + 63 < steps
             NB_TRY(run_graph(key, stream, [&](hipStream_t cs) {
                 for (int64_t k = 0; k < kGraphSteps; ++k) {
-                    const int st = step_launch(P, 1 + k, steps, cs);
-                    if (st != NBODY_OK) return st;
+                    const int b = (int)((1 + k) & 1);
+                    NB_TRY(force_and_step(P, P.buf[b], P.buf[b ^ 1], kClose | kOpen, cs));
                 }
                 return (int)NBODY_OK;
             }));
-        }
-        i = 1 + reps * kGraphSteps;
     }
     for (; i <= steps; ++i) NB_TRY(step_launch(P, i, steps, stream));
     return NBODY_OK;
@@ -584,7 +617,9 @@ size_t nbody_workspace_bytes(int32_t op, int64_t n_total, int32_t num_systems, i
 {
     if (n_total < 1 || n_total > kMaxBodies || num_systems < 1) return 0;
     if (op < NBODY_OP_ACCEL || op > NBODY_OP_RK4) return 0;
-    if (precision != NBODY_FP64 && precision != NBODY_SPLIT) return 0;
+    if (precision != NBODY_FP64 && precision != NBODY_SPLIT &&
+        precision != NBODY_SPLIT_COMPENSATED)
+        return 0;
     if (op == NBODY_OP_ADJOINT && (checkpoint_every < 1 || steps < 0)) return 0;
     return layout(op, n_total, num_systems, steps, checkpoint_every, precision).total;
 }
@@ -599,6 +634,7 @@ int32_t nbody_accel(const double* pos, const double* vel, const double* mass, in
     g_err.clear();
     NB_TRY(check_common(pos, mass, n, G));
     NB_TRY(check_prec(precision, small_mass));
+    NB_TRY(check_comp_size(precision, n));
     if (!acc_out) return fail(NBODY_EINVAL, "acc_out is NULL");
     const Layout L = layout(NBODY_OP_ACCEL, n, 1, 0, 1, precision);
     NB_TRY(check_ws(workspace, workspace_bytes, L.total));
@@ -644,7 +680,7 @@ int32_t nbody_accel(const double* pos, const double* vel, const double* mass, in
                                  at<int64_t>(workspace, L.nmaj), 0.0, kStoreAcc, acc_c, flags, s));
     } else {
         NB_HIP(launch_scale(mass_c, G, n, gm, s));
-        NB_HIP(launch_force(1, tile, pos_c, mass_c, gm, n, at<int64_t>(workspace, L.nmaj), G, part,
+        NB_HIP(launch_force(precision, tile, pos_c, mass_c, gm, n, at<int64_t>(workspace, L.nmaj), G, part,
                             s));
         NB_HIP(launch_step(part, chunks, nullptr, n, nullptr, nullptr, nullptr, acc_c, 0.0,
                            kStoreAcc, flags, s));
@@ -653,21 +689,30 @@ int32_t nbody_accel(const double* pos, const double* vel, const double* mass, in
     return NBODY_OK;
 }
 
-int32_t nbody_verlet_run(double* pos, double* vel, const double* mass, int64_t n, double G,
-                         double dt, int64_t steps, int32_t precision, double small_mass,
-                         void* workspace, size_t workspace_bytes, void* stream)
+}  // extern "C"
+
+namespace {
+
+// Checks the arguments of a velocity-Verlet run (the workspace excepted).
+int check_run(const double* pos, const double* vel, const double* mass, int64_t n, double G,
+              double dt, int64_t steps, int32_t precision, double small_mass)
 {
-    g_err.clear();
     NB_TRY(check_common(pos, mass, n, G));
     NB_TRY(check_prec(precision, small_mass));
+    NB_TRY(check_comp_size(precision, n));
     if (!vel) return fail(NBODY_EINVAL, "vel is NULL");
     if (steps < 0) return fail(NBODY_EINVAL, "steps must be >= 0");
     if (!std::isfinite(dt)) return fail(NBODY_EINVAL, "dt is not finite");
-    const Layout L = layout(NBODY_OP_RUN, n, 1, steps, 1, precision);
-    NB_TRY(check_ws(workspace, workspace_bytes, L.total));
-    if (steps == 0) return NBODY_OK;
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    return NBODY_OK;
+}
 
+// The step loop of nbody_verlet_run on the workspace `ws` (laid out as L),
+// replayed from graphs or enqueued directly.
+int verlet_run_on(double* pos, double* vel, const double* mass, int64_t n, double G, double dt,
+                  int64_t steps, int32_t precision, double small_mass, void* ws, const Layout& L,
+                  hipStream_t s, bool use_graph)
+{
+    if (steps == 0) return NBODY_OK;
     StepPlan P;
     P.prec = precision;
     P.tile = pick_tile(0, precision, n);
@@ -675,10 +720,10 @@ int32_t nbody_verlet_run(double* pos, double* vel, const double* mass, int64_t n
     P.n = n;
     P.G = G;
     P.dt = dt;
-    P.part = at<double>(workspace, L.part);
-    P.flags = at<uint32_t>(workspace, L.flags);
-    double* alt = at<double>(workspace, L.alt);
-    double* gm = at<double>(workspace, L.gm);
+    P.part = at<double>(ws, L.part);
+    P.flags = at<uint32_t>(ws, L.flags);
+    double* alt = at<double>(ws, L.alt);
+    double* gm = at<double>(ws, L.gm);
     P.gm = gm;
     const bool small = P.tile.variant == 3;
     if (precision == NBODY_FP64) {
@@ -690,27 +735,26 @@ int32_t nbody_verlet_run(double* pos, double* vel, const double* mass, int64_t n
         P.mass = mass;
         P.vel = vel;
         NB_HIP(launch_scale(mass, G, n, gm, s));
-        // r_steps must land in the caller's buffer: buf[steps & 1] = pos.
-        if (steps & 1) {
-            P.buf[0] = alt;
-            P.buf[1] = pos;
-            NB_HIP(hipMemcpyAsync(alt, pos, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        } else {
-            P.buf[0] = pos;
-            P.buf[1] = alt;
-        }
-        return run_steps(P, steps, s, true);
+        // r_0 in the caller's buffer, r_1 in the workspace's: the same roles
+        // for every run (the captured graphs do not depend on the step
+        // count); an odd run ends in the workspace's buffer and is copied
+        // back by a kernel (1.0 * x is exact)
+        P.buf[0] = pos;
+        P.buf[1] = alt;
+        NB_TRY(run_steps(P, steps, s, use_graph));
+        if (steps & 1) NB_HIP(launch_scale(alt, 1.0, 3 * n, pos, s));
+        return NBODY_OK;
     }
-    NB_TRY(split_prepare(workspace, L, mass, n, small_mass, s));
-    const int32_t* perm = at<int32_t>(workspace, L.perm);
-    double* pos_c = at<double>(workspace, L.pos_c);
-    double* vel_c = at<double>(workspace, L.vel_c);
-    double* mass_c = at<double>(workspace, L.mass_c);
-    double* alt_c = at<double>(workspace, L.alt_c);
+    NB_TRY(split_prepare(ws, L, mass, n, small_mass, s));
+    const int32_t* perm = at<int32_t>(ws, L.perm);
+    double* pos_c = at<double>(ws, L.pos_c);
+    double* vel_c = at<double>(ws, L.vel_c);
+    double* mass_c = at<double>(ws, L.mass_c);
+    double* alt_c = at<double>(ws, L.alt_c);
     NB_HIP(launch_gather(perm, n, pos, pos_c, 3, s));
     NB_HIP(launch_gather(perm, n, vel, vel_c, 3, s));
     NB_HIP(launch_gather(perm, n, mass, mass_c, 1, s));
-    P.nmaj = at<int64_t>(workspace, L.nmaj);
+    P.nmaj = at<int64_t>(ws, L.nmaj);
     if (small) {
         NB_HIP(launch_run_small(1, P.tile, pos_c, pos_c, vel_c, mass_c, n, P.nmaj, G, dt, 0, steps,
                                 steps, nullptr, nullptr, P.flags, s));
@@ -723,10 +767,26 @@ int32_t nbody_verlet_run(double* pos, double* vel, const double* mass, int64_t n
     P.vel = vel_c;
     P.buf[0] = pos_c;
     P.buf[1] = alt_c;
-    NB_TRY(run_steps(P, steps, s, true));
+    NB_TRY(run_steps(P, steps, s, use_graph));
     NB_HIP(launch_scatter(perm, n, P.buf[steps & 1], pos, 3, s));
     NB_HIP(launch_scatter(perm, n, vel_c, vel, 3, s));
     return NBODY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t nbody_verlet_run(double* pos, double* vel, const double* mass, int64_t n, double G,
+                         double dt, int64_t steps, int32_t precision, double small_mass,
+                         void* workspace, size_t workspace_bytes, void* stream)
+{
+    g_err.clear();
+    NB_TRY(check_run(pos, vel, mass, n, G, dt, steps, precision, small_mass));
+    const Layout L = layout(NBODY_OP_RUN, n, 1, steps, 1, precision);
+    NB_TRY(check_ws(workspace, workspace_bytes, L.total));
+    return verlet_run_on(pos, vel, mass, n, G, dt, steps, precision, small_mass, workspace, L,
+                         static_cast<hipStream_t>(stream), true);
 }
 
 int32_t nbody_rk4_run(double* pos, double* vel, const double* mass, int64_t n, double G,
@@ -736,6 +796,7 @@ int32_t nbody_rk4_run(double* pos, double* vel, const double* mass, int64_t n, d
     g_err.clear();
     NB_TRY(check_common(pos, mass, n, G));
     NB_TRY(check_prec(precision, small_mass));
+    NB_TRY(check_comp_size(precision, n));
     if (!vel) return fail(NBODY_EINVAL, "vel is NULL");
     if (steps < 0) return fail(NBODY_EINVAL, "steps must be >= 0");
     if (!std::isfinite(dt)) return fail(NBODY_EINVAL, "dt is not finite");
@@ -850,6 +911,7 @@ int32_t nbody_set_tile(int32_t kind, int32_t precision, int64_t n, const nbody_t
     if (kind == 2) n = 0;
     Tile t{tile_host->targets_per_lane, tile_host->waves, tile_host->chunks, tile_host->variant};
     if (!tile_supported(t) || (kind == 1 && (t.tpl > 2 || t.waves > 4 || t.variant > 1)) ||
+        (precision == NBODY_SPLIT_COMPENSATED && t.variant != 5) ||
         (t.variant == 3 && (kind != 0 || n > kSmallMax)) || (t.variant == 4 && kind != 0) ||
         (t.variant == 5 && !mutual_fits(kind, precision, n)))
         return fail(NBODY_EINVAL, "unsupported tile (%d, %d, %d, variant %d) for kind %d",
@@ -1212,6 +1274,7 @@ Tile batch_tile(int prec, const int64_t* offs, int32_t ns)
         sn2 += nk * nk;
         fits = fits && mutual_ranges(offs[k + 1] - offs[k]) <= kBatchSlots;
     }
+    if (prec == NBODY_SPLIT_COMPENSATED) return Tile{4, 4, 1, 5};   // each pair once only
     if (fits && sn2 >= (double)kBatchMutualMin * sn) return Tile{4, 4, 1, 5};
     return heuristic_tile(2, prec, 0);
 }
@@ -1224,6 +1287,10 @@ int batched_plan_upload(const int64_t* offsets_host, int32_t ns, const Tile& t_i
 {
     Tile t = t_in;
     auto bp = batch_plan(offsets_host, ns, t);
+    if (!bp && P->prec == NBODY_SPLIT_COMPENSATED)
+        return fail(NBODY_EUNSUPPORTED, "the compensated split form runs in the each-pair-once "
+                                        "pass, which takes ensembles of systems of at most "
+                                        "%d bodies", 256 * kBatchSlots);
     if (!bp) {
         t = heuristic_tile(2, P->prec, 0);   // one-way, always planned
         bp = batch_plan(offsets_host, ns, t);
@@ -1318,15 +1385,12 @@ int32_t nbody_verlet_run_batched(double* pos, double* vel, const double* mass,
         P.gm = gm;
         P.vel = vel;
         NB_HIP(launch_scale(mass, G, n, gm, s));
-        if (steps & 1) {
-            P.buf[0] = alt;
-            P.buf[1] = pos;
-            NB_HIP(hipMemcpyAsync(alt, pos, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        } else {
-            P.buf[0] = pos;
-            P.buf[1] = alt;
-        }
-        return run_steps(P, steps, s, true);
+        // fixed buffer roles (see verlet_run_on); an odd run is copied back
+        P.buf[0] = pos;
+        P.buf[1] = alt;
+        NB_TRY(run_steps(P, steps, s, true));
+        if (steps & 1) NB_HIP(launch_scale(alt, 1.0, 3 * n, pos, s));
+        return NBODY_OK;
     }
     NB_TRY(batched_split_prepare(pos, vel, mass, offsets_host, num_systems, G, small_mass,
                                  workspace, L, s, &P));
@@ -1367,14 +1431,19 @@ int32_t nbody_autotune_batched(int32_t precision, const double* pos, const doubl
         pos_w = P.buf[0];
     }
     std::vector<Tile> cands;
-    for (int tpl : {1, 2, 4})
-        for (int w : {1, 2, 4})
-            for (int v = 0; v < 3; ++v) cands.push_back(Tile{tpl, w, kBatchChunkMax, v});
+    if (precision != NBODY_SPLIT_COMPENSATED)   // (that form runs each pair once only)
+        for (int tpl : {1, 2, 4})
+            for (int w : {1, 2, 4})
+                for (int v = 0; v < 3; ++v) cands.push_back(Tile{tpl, w, kBatchChunkMax, v});
     bool fits = true;   // each pair once, if every system's ranges fit the slots
     for (int32_t k = 0; k < num_systems; ++k)
         fits = fits && mutual_ranges(offsets_host[k + 1] - offsets_host[k]) <= kBatchSlots;
     if (fits)
         for (const Tile& t : {Tile{2, 4, 1, 5}, Tile{4, 4, 1, 5}}) cands.push_back(t);
+    if (cands.empty())
+        return fail(NBODY_EUNSUPPORTED, "the compensated split form runs in the each-pair-once "
+                                        "pass, which takes ensembles of systems of at most "
+                                        "%d bodies", 256 * kBatchSlots);
     double* acc_w = at<double>(workspace, L.alt);
     // a candidate is timed as force pass and epilogue (the partial counts differ)
     auto pass = [&]() -> int {
@@ -1446,6 +1515,7 @@ int bench_prepare(int32_t kind, int32_t precision, const double* pos, const doub
 {
     NB_TRY(check_common(pos, mass, n, G));
     NB_TRY(check_prec(precision, small_mass));
+    NB_TRY(check_comp_size(precision, n));
     if (kind != 0 && kind != 1) return fail(NBODY_EINVAL, "kind must be 0 or 1");
     if (kind == 1 && precision != NBODY_FP64) return fail(NBODY_EINVAL, "the adjoint pass is FP64");
     const int op = kind == 0 ? NBODY_OP_ACCEL : NBODY_OP_ADJOINT;
@@ -1455,7 +1525,7 @@ int bench_prepare(int32_t kind, int32_t precision, const double* pos, const doub
     b->scratch = at<double>(workspace, L.alt);
     b->pos = pos;
     b->mass = mass;
-    if (precision == NBODY_SPLIT) {
+    if (precision != NBODY_FP64) {
         NB_TRY(split_prepare(workspace, L, mass, n, small_mass, s));
         const int32_t* perm = at<int32_t>(workspace, L.perm);
         NB_HIP(launch_gather(perm, n, pos, at<double>(workspace, L.pos_c), 3, s));
@@ -1558,15 +1628,16 @@ int32_t nbody_autotune(int32_t kind, int32_t precision, const double* pos, const
             }
         }
 
+    if (precision == NBODY_SPLIT_COMPENSATED) cands.clear();   // each pair once only
     if (mutual_fits(kind, precision, n))   // each pair once
         for (const Tile& t : {Tile{1, 4, 1, 5}, Tile{2, 2, 1, 5}, Tile{2, 4, 1, 5}, Tile{4, 4, 1, 5}})
             cands.push_back(t);
-    if (kind == 0 && n <= kFusedMax) {
+    if (kind == 0 && n <= kFusedMax && precision != NBODY_SPLIT_COMPENSATED) {
         // force pass and step in one kernel, waves of a group splitting the sources
         for (int tpl : {1, 2})
             for (int w : {2, 4, 8}) cands.push_back(Tile{tpl, w, 1, 4});
     }
-    if (kind == 0 && n <= kSmallMax) {
+    if (kind == 0 && n <= kSmallMax && precision != NBODY_SPLIT_COMPENSATED) {
         // single workgroup: force pass, reduction and store in one launch
         for (int S : {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 16, 24, 32, 48, 64}) {
             const Tile t{1, 16, S, 3};

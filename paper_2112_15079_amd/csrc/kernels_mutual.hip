@@ -179,6 +179,132 @@ __device__ __forceinline__ void tile_sweep32(const double* __restrict__ sx,
     }
 }
 
+// Kahan's compensated addition of the FP32 product a * b: s + a b with the
+// rounding error carried in c (the product rounded once, inside the FMA).
+__device__ __forceinline__ void kahan_fma(float& s, float& c, float a, float b)
+{
+    const float y = __builtin_fmaf(a, b, -c);
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// Per-lane FP32 Kahan sums of the three components.
+struct Kahan3 {
+    float s[3], c[3];
+};
+
+__device__ __forceinline__ void k3_zero(Kahan3& k)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { k.s[i] = 0.f; k.c[i] = 0.f; }
+}
+
+// The compensated split form (precision 2): the FP64 displacement d and
+// squared distance r2; |d|^-3 = y^3 from the FP32 reciprocal square root y0
+// of float(r2) refined by one Newton step in FP64, y = y0 (1 + e / 2),
+// e = 1 - r2 y0^2 (for every pair); a light source's term on a target (a
+// light target's reaction on a source) rounded to FP32 as
+// float(G m f) * float(d) and added to an FP32 Kahan sum; a heavy body's
+// term added in FP64.  MIXED: bodies of either class may meet in this tile
+// (class by index: below n_major is heavy); otherwise every body is light
+// and only the FP32 sums are kept.  The target sums (ka) run over the whole
+// sweep of the workgroup; each reaction's (16 targets of a row) is added to
+// the FP64 reaction sums in LDS as s - c.  Tile geometry as tile_sweep.
+template <int KMT, int NSYM, bool DIAG, bool MIXED>
+__device__ __forceinline__ void tile_sweep_comp(const double* __restrict__ sx,
+                                                const double* __restrict__ sy,
+                                                const double* __restrict__ sz,
+                                                const double* __restrict__ sg,
+                                                double* __restrict__ ra, int lane,
+                                                const Body (&tg)[KMT], const bool (&theavy)[KMT],
+                                                int64_t jbase, int64_t n_major,
+                                                double (&ax)[KMT], double (&ay)[KMT],
+                                                double (&az)[KMT], Kahan3 (&ka)[KMT])
+{
+    constexpr bool kReact = NSYM > 0;
+    const int row = lane >> 4;
+    const int col = lane & 15;
+    for (int q = 0; q < 4; ++q) {
+        const int grp = (row + q) & 3;
+        const int home = 16 * grp + col;
+        double rx = 0.0, ry = 0.0, rz = 0.0;
+        Kahan3 kr;
+        k3_zero(kr);
+#pragma unroll 2
+        for (int k = 0; k < 16; ++k) {
+            const int jj = 32 * grp + col + k;
+            const double jx = sx[jj], jy = sy[jj], jz = sz[jj], jg = sg[jj];
+            const bool jheavy = MIXED && jbase + 16 * grp + ((col + k) & 15) < n_major;
+#pragma unroll
+            for (int t = 0; t < KMT; ++t) {
+                if (t > NSYM || (t == NSYM && !DIAG)) continue;
+                if (t == NSYM && q == 0 && k == 0) continue;   // the target itself
+                const double dx = jx - tg[t].x;
+                const double dy = jy - tg[t].y;
+                const double dz = jz - tg[t].z;
+                const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+                const double y0 = (double)__builtin_amdgcn_rsqf((float)r2);
+                const double e = __builtin_fma(-r2, y0 * y0, 1.0);
+                const double y = __builtin_fma(y0 * e, 0.5, y0);
+                const double f = y * y * y;   // |d|^-3
+                const float dx32 = (float)dx, dy32 = (float)dy, dz32 = (float)dz;
+                const double fi = jg * f;
+                if (MIXED) {
+                    const double wi = jheavy ? fi : 0.0;
+                    const float fi32 = jheavy ? 0.f : (float)fi;
+                    ax[t] = __builtin_fma(wi, dx, ax[t]);
+                    ay[t] = __builtin_fma(wi, dy, ay[t]);
+                    az[t] = __builtin_fma(wi, dz, az[t]);
+                    kahan_fma(ka[t].s[0], ka[t].c[0], fi32, dx32);
+                    kahan_fma(ka[t].s[1], ka[t].c[1], fi32, dy32);
+                    kahan_fma(ka[t].s[2], ka[t].c[2], fi32, dz32);
+                } else {
+                    const float fi32 = (float)fi;
+                    kahan_fma(ka[t].s[0], ka[t].c[0], fi32, dx32);
+                    kahan_fma(ka[t].s[1], ka[t].c[1], fi32, dy32);
+                    kahan_fma(ka[t].s[2], ka[t].c[2], fi32, dz32);
+                }
+                if (t < NSYM) {   // reaction on the source
+                    const double fj = tg[t].gm * f;
+                    if (MIXED) {
+                        const double wj = theavy[t] ? fj : 0.0;
+                        const float fj32 = theavy[t] ? 0.f : (float)fj;
+                        rx = __builtin_fma(-wj, dx, rx);
+                        ry = __builtin_fma(-wj, dy, ry);
+                        rz = __builtin_fma(-wj, dz, rz);
+                        kahan_fma(kr.s[0], kr.c[0], -fj32, dx32);
+                        kahan_fma(kr.s[1], kr.c[1], -fj32, dy32);
+                        kahan_fma(kr.s[2], kr.c[2], -fj32, dz32);
+                    } else {
+                        const float fj32 = (float)fj;
+                        kahan_fma(kr.s[0], kr.c[0], -fj32, dx32);
+                        kahan_fma(kr.s[1], kr.c[1], -fj32, dy32);
+                        kahan_fma(kr.s[2], kr.c[2], -fj32, dz32);
+                    }
+                }
+            }
+            if (kReact) {
+                if (MIXED) {
+                    rx = row_next(rx);
+                    ry = row_next(ry);
+                    rz = row_next(rz);
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    kr.s[i] = row_next32(kr.s[i]);
+                    kr.c[i] = row_next32(kr.c[i]);
+                }
+            }
+        }
+        if (kReact) {
+            ra[home] += rx + ((double)kr.s[0] - (double)kr.c[0]);
+            ra[64 + home] += ry + ((double)kr.s[1] - (double)kr.c[1]);
+            ra[128 + home] += rz + ((double)kr.s[2] - (double)kr.c[2]);
+        }
+    }
+}
+
 // One tile sweep: the KMT targets of this lane (target blocks I0 .. I0+KMT-1)
 // against one source block J staged in LDS as four groups of 16 sources,
 // each stored twice in a row (s*[32*grp + i], i < 32).  Targets t < NSYM lie
@@ -300,6 +426,49 @@ __device__ __forceinline__ void sweep_dispatch32(int d, const double* px, const 
     }
 }
 
+template <int KMT, bool MIXED>
+__device__ __forceinline__ void sweep_dispatch_comp(int d, const double* px, const double* py,
+                                                    const double* pz, const double* pg,
+                                                    double* ra, int lane, const Body (&tg)[KMT],
+                                                    const bool (&th)[KMT], int64_t jbase,
+                                                    int64_t n_major, double (&ax)[KMT],
+                                                    double (&ay)[KMT], double (&az)[KMT],
+                                                    Kahan3 (&ka)[KMT])
+{
+    if (d >= KMT) {
+        tile_sweep_comp<KMT, KMT, false, MIXED>(px, py, pz, pg, ra, lane, tg, th, jbase, n_major,
+                                                ax, ay, az, ka);
+        return;
+    }
+    switch (d) {
+    case 0: tile_sweep_comp<KMT, 0, true, MIXED>(px, py, pz, pg, ra, lane, tg, th, jbase, n_major, ax, ay, az, ka); break;
+    case 1: tile_sweep_comp<KMT, (KMT > 1 ? 1 : 0), true, MIXED>(px, py, pz, pg, ra, lane, tg, th, jbase, n_major, ax, ay, az, ka); break;
+    case 2: tile_sweep_comp<KMT, (KMT > 2 ? 2 : 0), true, MIXED>(px, py, pz, pg, ra, lane, tg, th, jbase, n_major, ax, ay, az, ka); break;
+    case 3: tile_sweep_comp<KMT, (KMT > 3 ? 3 : 0), true, MIXED>(px, py, pz, pg, ra, lane, tg, th, jbase, n_major, ax, ay, az, ka); break;
+    default: break;
+    }
+}
+
+// The compensated split form's sweep of one tile by a wave holding target
+// blocks I0 .. I0 + KT - 1 (light: no heavy body among them or the sources).
+template <int KT>
+__device__ __forceinline__ void sweep_comp(bool light, int d, int I0, int J, int lane,
+                                           const double* px, const double* py, const double* pz,
+                                           const double* pg, double* ra, const Body (&tg)[KT],
+                                           int64_t n_major, double (&ax)[KT], double (&ay)[KT],
+                                           double (&az)[KT], Kahan3 (&ka)[KT])
+{
+    bool th[KT];
+#pragma unroll
+    for (int t = 0; t < KT; ++t) th[t] = (int64_t)(I0 + t) * 64 + lane < n_major;
+    if (light)
+        sweep_dispatch_comp<KT, false>(d, px, py, pz, pg, ra, lane, tg, th, (int64_t)J * 64,
+                                       n_major, ax, ay, az, ka);
+    else
+        sweep_dispatch_comp<KT, true>(d, px, py, pz, pg, ra, lane, tg, th, (int64_t)J * 64,
+                                      n_major, ax, ay, az, ka);
+}
+
 // Which workgroups run whole range pairs and which run halves (see the top
 // of the file).  D = 0: every pair whole.
 struct MutualTail {
@@ -364,7 +533,7 @@ __host__ __device__ inline void mt_decode(const MutualTail& tl, int64_t bid, int
 // Half `half` of the split pair (g, r), r > g: target blocks 4g + 2 half and
 // 4g + 2 half + 1 (two per lane) against source block 4r + w in wave w.  The
 // LDS arrays are the whole-pair workgroup's (same sizes or larger).
-template <bool SPLIT>
+template <int PREC>
 __device__ __forceinline__ void mutual_half_body(const double* __restrict__ pos,
                                                  const double* __restrict__ gm, int64_t n,
                                                  int64_t n_major, int g, int r, int half,
@@ -375,6 +544,7 @@ __device__ __forceinline__ void mutual_half_body(const double* __restrict__ pos,
                                                  double* combp)
 {
     constexpr int KT = 2;
+    constexpr bool SPLIT = PREC == 1;   // the FP32 tiles (light sources' G m as floats)
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int nb = (int)((n + 63) / 64);
@@ -385,11 +555,13 @@ __device__ __forceinline__ void mutual_half_body(const double* __restrict__ pos,
     Body tg[KT];
     float tgf[KT];
     double ax[KT], ay[KT], az[KT];
+    Kahan3 ka[KT];
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
         tg[t] = load_body(pos, gm, n, n, (int64_t)(I0 + t) * 64 + lane);
         tgf[t] = (float)tg[t].gm;
         ax[t] = 0.0; ay[t] = 0.0; az[t] = 0.0;
+        k3_zero(ka[t]);
     }
     {
         const Body b = load_body(pos, gm, n, n, (int64_t)J * 64 + lane);
@@ -406,15 +578,27 @@ __device__ __forceinline__ void mutual_half_body(const double* __restrict__ pos,
         racc[w][1][lane] = 0.0;
         racc[w][2][lane] = 0.0;
     }
-    const bool fp32 = SPLIT && I0 >= (int)((n_major + 63) / 64);
+    const bool fp32 = PREC != 0 && I0 >= (int)((n_major + 63) / 64);
     __syncthreads();
-    if (J < nb) {   // r > g: J - I0 >= 2, every tile both ways
+    if (PREC == 2) {
+        if (J < nb)
+            sweep_comp<KT>(fp32, J - I0, I0, J, lane, sx[w], sy[w], sz[w], sg[w], &racc[w][0][0], tg,
+                           n_major, ax, ay, az, ka);
+    } else if (J < nb) {   // r > g: J - I0 >= 2, every tile both ways
         if (fp32)
             sweep_dispatch32<KT>(J - I0, sx[w], sy[w], sz[w], sgf[SPLIT ? w : 0], &racc[w][0][0],
                                  lane, tg, tgf, ax, ay, az);
         else
             sweep_dispatch<KT>(J - I0, sx[w], sy[w], sz[w], sg[w], &racc[w][0][0], lane, tg, ax,
                                ay, az, PolyConst{vreg_const(1.875), vreg_const(1.5)});
+    }
+    if (PREC == 2) {
+#pragma unroll
+        for (int t = 0; t < KT; ++t) {
+            ax[t] += (double)ka[t].s[0] - (double)ka[t].c[0];
+            ay[t] += (double)ka[t].s[1] - (double)ka[t].c[1];
+            az[t] += (double)ka[t].s[2] - (double)ka[t].c[2];
+        }
     }
     // the four waves' target sums, added in wave order
     double (*comb)[KT][3][64] = reinterpret_cast<double (*)[KT][3][64]>(combp);
@@ -462,7 +646,7 @@ __device__ __forceinline__ void mutual_half_body(const double* __restrict__ pos,
 // half >= 0 runs that half of a split pair instead (single systems, stride
 // n, shape (4, 4)); the diagonal workgroup zero-fills the extra slots of
 // `tl` that no split pair writes.
-template <int KMT, int KMW, bool SPLIT>
+template <int KMT, int KMW, int PREC>
 __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
                                             const double* __restrict__ gm, int64_t n,
                                             int64_t stride, int64_t n_major, int g, int r,
@@ -470,6 +654,7 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
                                             int half, int xslot)
 {
     using Shape = MutualShape<KMT, KMW>;
+    constexpr bool SPLIT = PREC == 1;   // the FP32 tiles (light sources' G m as floats)
     __shared__ double sx[kMM][128], sy[kMM][128], sz[kMM][128], sg[kMM][128];
     __shared__ float sgf[SPLIT ? kMM : 1][128];
     __shared__ double racc[kMM][3][64];
@@ -477,7 +662,7 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
     if constexpr (KMT == 4 && KMW == 4) {
         static_assert(sizeof(comb) >= 3 * 2 * 3 * 64 * sizeof(double), "half-pair sums fit");
         if (half >= 0) {
-            mutual_half_body<SPLIT>(pos, gm, n, n_major, g, r, half, xslot, part, sx, sy, sz, sg,
+            mutual_half_body<PREC>(pos, gm, n, n_major, g, r, half, xslot, part, sx, sy, sz, sg,
                                     SPLIT ? sgf : nullptr, racc, &comb[0][0][0][0][0]);
             return;
         }
@@ -494,10 +679,12 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
 
     Body tg[KMT];
     double ax[KMT], ay[KMT], az[KMT];
+    Kahan3 ka[KMT];
 #pragma unroll
     for (int t = 0; t < KMT; ++t) {
         tg[t] = load_body(pos, gm, n, stride, (int64_t)(I0 + t) * 64 + lane);
         ax[t] = 0.0; ay[t] = 0.0; az[t] = 0.0;
+        k3_zero(ka[t]);
     }
 
     // stage the source blocks (wave w: blocks w, w + KMW, ...): four groups
@@ -523,10 +710,25 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
     for (int t = 0; t < KMT; ++t) tgf[t] = (float)tg[t].gm;
     // split form: waves whose target blocks start below the first block
     // free of heavy bodies stay in FP64
-    const bool fp32 = SPLIT && I0 >= (int)((n_major + 63) / 64);
+    const bool fp32 = PREC != 0 && I0 >= (int)((n_major + 63) / 64);
     __syncthreads();
 
-    if (fp32) {
+    if constexpr (PREC == 2) {
+        for (int p = 0; p < Shape::kPhases; ++p) {
+            const int jb = (w + p) % kMM;
+            const int J = J0 + jb;
+            if (J < nb && J >= I0)
+                sweep_comp<KMT>(fp32, J - I0, I0, J, lane, sx[jb], sy[jb], sz[jb], sg[jb],
+                                &racc[jb][0][0], tg, n_major, ax, ay, az, ka);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int t = 0; t < KMT; ++t) {
+            ax[t] += (double)ka[t].s[0] - (double)ka[t].c[0];
+            ay[t] += (double)ka[t].s[1] - (double)ka[t].c[1];
+            az[t] += (double)ka[t].s[2] - (double)ka[t].c[2];
+        }
+    } else if (fp32) {
         for (int p = 0; p < Shape::kPhases; ++p) {
             const int jb = (w + p) % kMM;
             const int J = J0 + jb;
@@ -619,7 +821,7 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
     }
 }
 
-template <int KMT, int KMW, bool SPLIT>
+template <int KMT, int KMW, int PREC>
 __global__ __launch_bounds__(64 * KMW) void k_force_mutual(const double* __restrict__ pos,
                                                            const double* __restrict__ gm,
                                                            int64_t n,
@@ -629,12 +831,13 @@ __global__ __launch_bounds__(64 * KMW) void k_force_mutual(const double* __restr
 {
     int g, r, half, xslot;
     mt_decode(tl, blockIdx.x, g, r, half, xslot);
-    mutual_unit<KMT, KMW, SPLIT>(pos, gm, n, n, SPLIT ? nmaj[0] : 0, g, r, part, tl, half, xslot);
+    mutual_unit<KMT, KMW, PREC>(pos, gm, n, n, PREC != 0 ? nmaj[0] : 0, g, r, part, tl, half,
+                                xslot);
 }
 
 // The ensemble: one workgroup per unit (system, g = tblock, r = chunk) of the
 // work list; the partial planes span all systems (stride n_total).
-template <int KMT, int KMW, bool SPLIT>
+template <int KMT, int KMW, int PREC>
 __global__ __launch_bounds__(64 * KMW) void k_force_mutual_batched(
     const double* __restrict__ pos, const double* __restrict__ gm, int64_t n_total,
     const BatchUnit* __restrict__ units, const int64_t* __restrict__ nmaj,
@@ -642,9 +845,9 @@ __global__ __launch_bounds__(64 * KMW) void k_force_mutual_batched(
 {
     const BatchUnit u = units[blockIdx.x];
     const MutualTail whole{u.chunks, 0, 0, 0};
-    mutual_unit<KMT, KMW, SPLIT>(pos + u.body0, gm + u.body0, u.n, n_total,
-                                 SPLIT ? nmaj[u.sys] : 0, u.tblock, u.chunk, part + u.body0,
-                                 whole, -1, 0);
+    mutual_unit<KMT, KMW, PREC>(pos + u.body0, gm + u.body0, u.n, n_total,
+                                PREC != 0 ? nmaj[u.sys] : 0, u.tblock, u.chunk, part + u.body0,
+                                whole, -1, 0);
 }
 
 }  // namespace
@@ -693,43 +896,43 @@ bool mutual_shape_supported(int tpl, int waves)
            (tpl == 4 && waves == 4);
 }
 
-template <bool SPLIT>
+template <int PREC>
 static void launch_mutual_shape(int tpl, int waves, dim3 grid, const double* pos, const double* gm,
                                 int64_t n, const int64_t* nmaj, const MutualTail& tl,
                                 double* part, hipStream_t s)
 {
     const dim3 block((unsigned)(64 * waves));
     if (tpl == 1)
-        hipLaunchKernelGGL((k_force_mutual<1, 4, SPLIT>), grid, block, 0, s, pos, gm, n, nmaj,
+        hipLaunchKernelGGL((k_force_mutual<1, 4, PREC>), grid, block, 0, s, pos, gm, n, nmaj,
                            tl, part);
     else if (tpl == 2 && waves == 2)
-        hipLaunchKernelGGL((k_force_mutual<2, 2, SPLIT>), grid, block, 0, s, pos, gm, n, nmaj,
+        hipLaunchKernelGGL((k_force_mutual<2, 2, PREC>), grid, block, 0, s, pos, gm, n, nmaj,
                            tl, part);
     else if (tpl == 2)
-        hipLaunchKernelGGL((k_force_mutual<2, 4, SPLIT>), grid, block, 0, s, pos, gm, n, nmaj,
+        hipLaunchKernelGGL((k_force_mutual<2, 4, PREC>), grid, block, 0, s, pos, gm, n, nmaj,
                            tl, part);
     else
-        hipLaunchKernelGGL((k_force_mutual<4, 4, SPLIT>), grid, block, 0, s, pos, gm, n, nmaj,
+        hipLaunchKernelGGL((k_force_mutual<4, 4, PREC>), grid, block, 0, s, pos, gm, n, nmaj,
                            tl, part);
 }
 
-template <bool SPLIT>
+template <int PREC>
 static void launch_mutual_batched_shape(int tpl, int waves, dim3 grid, const double* pos,
                                         const double* gm, int64_t n_total, const BatchUnit* units,
                                         const int64_t* nmaj, double* part, hipStream_t s)
 {
     const dim3 block((unsigned)(64 * waves));
     if (tpl == 1)
-        hipLaunchKernelGGL((k_force_mutual_batched<1, 4, SPLIT>), grid, block, 0, s, pos, gm,
+        hipLaunchKernelGGL((k_force_mutual_batched<1, 4, PREC>), grid, block, 0, s, pos, gm,
                            n_total, units, nmaj, part);
     else if (tpl == 2 && waves == 2)
-        hipLaunchKernelGGL((k_force_mutual_batched<2, 2, SPLIT>), grid, block, 0, s, pos, gm,
+        hipLaunchKernelGGL((k_force_mutual_batched<2, 2, PREC>), grid, block, 0, s, pos, gm,
                            n_total, units, nmaj, part);
     else if (tpl == 2)
-        hipLaunchKernelGGL((k_force_mutual_batched<2, 4, SPLIT>), grid, block, 0, s, pos, gm,
+        hipLaunchKernelGGL((k_force_mutual_batched<2, 4, PREC>), grid, block, 0, s, pos, gm,
                            n_total, units, nmaj, part);
     else
-        hipLaunchKernelGGL((k_force_mutual_batched<4, 4, SPLIT>), grid, block, 0, s, pos, gm,
+        hipLaunchKernelGGL((k_force_mutual_batched<4, 4, PREC>), grid, block, 0, s, pos, gm,
                            n_total, units, nmaj, part);
 }
 
@@ -739,15 +942,16 @@ hipError_t launch_force_mutual_batched(int precision, int tpl, int waves, const 
                                        hipStream_t s)
 {
     if (!gm || !units || num_units < 1 || !mutual_shape_supported(tpl, waves) ||
-        (precision != 0 && !nmaj))
+        precision < 0 || precision > 2 || (precision != 0 && !nmaj))
         return hipErrorInvalidValue;
     const dim3 grid((unsigned)num_units);
     if (precision == 0)
-        launch_mutual_batched_shape<false>(tpl, waves, grid, pos, gm, n_total, units, nullptr,
-                                           part, s);
+        launch_mutual_batched_shape<0>(tpl, waves, grid, pos, gm, n_total, units, nullptr, part,
+                                       s);
+    else if (precision == 1)
+        launch_mutual_batched_shape<1>(tpl, waves, grid, pos, gm, n_total, units, nmaj, part, s);
     else
-        launch_mutual_batched_shape<true>(tpl, waves, grid, pos, gm, n_total, units, nmaj, part,
-                                          s);
+        launch_mutual_batched_shape<2>(tpl, waves, grid, pos, gm, n_total, units, nmaj, part, s);
     return hipGetLastError();
 }
 
@@ -755,15 +959,18 @@ hipError_t launch_force_mutual(int precision, int tpl, int waves, const double* 
                                const double* gm, int64_t n, const int64_t* nmaj, double* part,
                                hipStream_t s)
 {
-    if (!gm || n < 1 || !mutual_shape_supported(tpl, waves) || (precision != 0 && !nmaj))
+    if (!gm || n < 1 || !mutual_shape_supported(tpl, waves) || precision < 0 || precision > 2 ||
+        (precision != 0 && !nmaj))
         return hipErrorInvalidValue;
     const MutualTail tl = mutual_tail(n, tpl, waves);
     const int64_t pairs = (int64_t)tl.R * (tl.R + 1) / 2;
     const dim3 grid((unsigned)(tl.F + 2 * (pairs - tl.F)));   // whole pairs, then halves
     if (precision == 0)
-        launch_mutual_shape<false>(tpl, waves, grid, pos, gm, n, nullptr, tl, part, s);
+        launch_mutual_shape<0>(tpl, waves, grid, pos, gm, n, nullptr, tl, part, s);
+    else if (precision == 1)
+        launch_mutual_shape<1>(tpl, waves, grid, pos, gm, n, nmaj, tl, part, s);
     else
-        launch_mutual_shape<true>(tpl, waves, grid, pos, gm, n, nmaj, tl, part, s);
+        launch_mutual_shape<2>(tpl, waves, grid, pos, gm, n, nmaj, tl, part, s);
     return hipGetLastError();
 }
 

@@ -13,9 +13,12 @@ import json
 import torch
 
 from . import _capi as C
-from ._capi import NBODY_FP64, NBODY_SPLIT
+from ._capi import NBODY_FP64, NBODY_SPLIT, NBODY_SPLIT_COMPENSATED
 
-_PREC = {"fp64": NBODY_FP64, "split": NBODY_SPLIT, NBODY_FP64: NBODY_FP64, NBODY_SPLIT: NBODY_SPLIT}
+_PREC = {"fp64": NBODY_FP64, "split": NBODY_SPLIT, "compensated": NBODY_SPLIT_COMPENSATED,
+         NBODY_FP64: NBODY_FP64, NBODY_SPLIT: NBODY_SPLIT,
+         NBODY_SPLIT_COMPENSATED: NBODY_SPLIT_COMPENSATED}
+_PREC_NAME = {NBODY_FP64: "fp64", NBODY_SPLIT: "split", NBODY_SPLIT_COMPENSATED: "compensated"}
 
 #: 3e17 kg in solar masses (1 Msun = 1.98847e30 kg): the small-body class
 #: boundary for the split form in AU / day / Msun units.
@@ -26,7 +29,7 @@ def _prec(p) -> int:
     try:
         return _PREC[p]
     except KeyError:
-        raise ValueError(f"precision must be 'fp64' or 'split', got {p!r}") from None
+        raise ValueError(f"precision must be 'fp64', 'split' or 'compensated', got {p!r}") from None
 
 
 def _state(t: torch.Tensor, name: str, n: int | None = None, planes: int = 3) -> torch.Tensor:
@@ -60,7 +63,7 @@ def _same_device(*ts):
 
 
 def _small(precision: int, small_mass):
-    if precision == NBODY_SPLIT:
+    if precision != NBODY_FP64:
         return float(SMALL_MASS_MSUN if small_mass is None else small_mass)
     return 0.0
 
@@ -275,7 +278,7 @@ def autotune(pos, mass, G, precision="fp64", kind=0, small_mass=None):
                                  _small(p, small_mass), ws.data_ptr(), ws.numel(),
                                  C.stream_handle(dev), ctypes.byref(t), ctypes.byref(ms))
     C.check(st, "nbody_autotune")
-    _tuned[(int(kind), "fp64" if p == NBODY_FP64 else "split", n)] = t.as_dict()
+    _tuned[(int(kind), _PREC_NAME[p], n)] = t.as_dict()
     return t.as_dict(), float(ms.value)
 
 
@@ -297,7 +300,7 @@ def autotune_batched(pos, mass, offsets, G, precision="fp64", small_mass=None):
                                          _small(p, small_mass), ws.data_ptr(), ws.numel(),
                                          C.stream_handle(dev), ctypes.byref(t), ctypes.byref(ms))
     C.check(st, "nbody_autotune_batched")
-    _tuned[(2, "fp64" if p == NBODY_FP64 else "split", 0)] = t.as_dict()
+    _tuned[(2, _PREC_NAME[p], 0)] = t.as_dict()
     return t.as_dict(), float(ms.value)
 
 

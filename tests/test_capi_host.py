@@ -112,7 +112,7 @@ def test_rk4_rejects_bad_arguments():
     assert lib.nbody_rk4_run(FAKE, None, FAKE, 5, 1.0, 0.1, 3, 0, 0.0, ws, big, None) == C.NBODY_EINVAL
     assert lib.nbody_rk4_run(FAKE, FAKE, FAKE, 5, 1.0, 0.1, -1, 0, 0.0, ws, big, None) == C.NBODY_EINVAL
     assert lib.nbody_rk4_run(FAKE, FAKE, FAKE, 5, 1.0, float("nan"), 3, 0, 0.0, ws, big, None) == C.NBODY_EINVAL
-    assert lib.nbody_rk4_run(FAKE, FAKE, FAKE, 5, 1.0, 0.1, 3, 2, 0.0, ws, big, None) == C.NBODY_EINVAL
+    assert lib.nbody_rk4_run(FAKE, FAKE, FAKE, 5, 1.0, 0.1, 3, 3, 0.0, ws, big, None) == C.NBODY_EINVAL
     assert lib.nbody_rk4_run(FAKE, FAKE, FAKE, 5, 1.0, 0.1, 3, 0, 0.0, ws, 64, None) == C.NBODY_EWORKSPACE
     assert lib.nbody_rk4_run(FAKE, FAKE, FAKE, 5, 1.0, 0.1, 0, 0, 0.0, ws, big, None) == C.NBODY_OK
 
@@ -249,3 +249,41 @@ def test_python_wrapper_rejects_cpu_tensors():
         nb.accel(pos, mass.float(), 1.0)
     with pytest.raises(ValueError):
         nb.accel(pos, mass, 1.0, precision="fp16")
+
+
+def test_compensated_split_form_host_rules():
+    """Precision 2 (the split form with FP64-refined factors and Kahan-
+    compensated FP32 light terms) runs in the each-pair-once pass only: its
+    tile is variant 5 at every size, other variants are refused, and systems
+    beyond 131,072 bodies are refused before anything is enqueued."""
+    lib = _lib()
+    lib.nbody_reset_caches()
+    t = C.Tile()
+    for n in (1, 10, 131, 600, 10425, 131072):
+        assert lib.nbody_get_tile(0, C.NBODY_SPLIT_COMPENSATED, n, ctypes.byref(t)) == C.NBODY_OK
+        assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == (4, 4, 1, 5), n
+    assert lib.nbody_get_tile(2, C.NBODY_SPLIT_COMPENSATED, 0, ctypes.byref(t)) == C.NBODY_OK
+    assert t.variant == 5
+    for bad in [(1, 2, 9, 1), (1, 16, 2, 3), (1, 8, 1, 4), (2, 1, 3, 0)]:
+        assert lib.nbody_set_tile(0, C.NBODY_SPLIT_COMPENSATED, 10425,
+                                  ctypes.byref(C.Tile(*bad))) == C.NBODY_EINVAL, bad
+    assert lib.nbody_set_tile(0, C.NBODY_SPLIT_COMPENSATED, 10425,
+                              ctypes.byref(C.Tile(2, 4, 1, 5))) == C.NBODY_OK
+    assert lib.nbody_get_tile(0, C.NBODY_SPLIT_COMPENSATED, 10425, ctypes.byref(t)) == C.NBODY_OK
+    assert (t.targets_per_lane, t.waves, t.variant) == (2, 4, 5)
+    lib.nbody_reset_caches()
+    ws = ctypes.c_void_p(0x100000)
+    big = 1 << 40
+    for fn, args in (("nbody_accel", (FAKE, None, FAKE, 131073, 1.0, 0.0, 0, FAKE, 2, 0.0)),
+                     ("nbody_verlet_run", (FAKE, FAKE, FAKE, 131073, 1.0, 0.1, 10, 2, 0.0)),
+                     ("nbody_rk4_run", (FAKE, FAKE, FAKE, 131073, 1.0, 0.1, 10, 2, 0.0))):
+        assert getattr(lib, fn)(*args, ws, big, None) == C.NBODY_EUNSUPPORTED, fn
+        assert "compensated" in C.last_error()
+    # a negative threshold is refused as for the split form
+    assert lib.nbody_accel(FAKE, None, FAKE, 5, 1.0, 0.0, 0, FAKE, 2, -1.0, ws, big,
+                           None) == C.NBODY_EINVAL
+    ws_bytes = lib.nbody_workspace_bytes
+    for op in (C.OP_ACCEL, C.OP_RUN, C.OP_RK4, C.OP_BATCHED):
+        assert ws_bytes(op, 10425, 1, 0, 1, C.NBODY_SPLIT_COMPENSATED) == \
+            ws_bytes(op, 10425, 1, 0, 1, C.NBODY_SPLIT) > 0
+

@@ -112,13 +112,14 @@ def test_adjoint_autotune_then_parity():
     nb.reset_caches()
 
 
-def test_adjoint_full_size_prefix_matches_oracle():
+@pytest.mark.parametrize("steps", [150, 1000])
+def test_adjoint_full_size_prefix_matches_oracle(steps):
     """The 2,079-body adjoint workload at full size in the benchmark's launch
-    configuration (default tiles, checkpoints every 100 steps, ragged last
-    segment), over a 150-step prefix, against the oracle's reverse sweep."""
+    configuration (default tiles, checkpoints every 100 steps; a ragged last
+    segment at 150 steps), over a 150- and a 1000-step prefix, against the
+    oracle's reverse sweep."""
     nb.reset_caches()
     s = S.config(4)
-    steps = 150
     first = 1 + s.counts["major"]
     rng = np.random.default_rng(250)
     lr = np.zeros((3, s.n))

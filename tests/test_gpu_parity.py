@@ -520,7 +520,38 @@ def test_split_131072_sampled_error():
     assert e <= 2e-12
 
 
-@pytest.mark.parametrize("k,steps", [(0, 3650), (1, 200)])
+def test_split_vs_fp64_131072_full_run():
+    """The 131,072-body workload run for its full 1000 steps in FP64 and in
+    the split form from the same state: the final energies agree to 1e-10 of
+    |E(0)|, and the split form's per-step accelerations (at the initial
+    state and at its own final state) are within 2e-12 of the oracle on 258
+    sampled targets, the FP64 form's within 1e-13."""
+    s = S.config(2)
+    assert s.n == 131072
+    m = T(s.mass)
+    E0 = H(nb.energy(T(s.pos), T(s.vel), m, s.G))[2]
+    runs = {}
+    for prec in ("fp64", "split"):
+        p, v = T(s.pos), T(s.vel)
+        nb.verlet_run(p, v, m, s.G, s.dt, 1000, precision=prec)
+        runs[prec] = (p, v, H(nb.energy(p, v, m, s.G))[2])
+    d = abs(runs["split"][2] - runs["fp64"][2]) / abs(E0)
+    log(f"n=131072, 1000 steps: |E_split - E_fp64|/|E0| = {d:.2e}, "
+        f"fp64 dE/E = {(runs['fp64'][2] - E0) / abs(E0):.2e}")
+    assert d <= 1e-10
+    rng = np.random.default_rng(11)
+    idx = np.unique(np.concatenate([[0, 1, 30, 149, 150, s.n - 1],
+                                    rng.choice(s.n, 252, replace=False)]))
+    assert idx.size >= 256
+    for label, pos in (("initial", s.pos), ("final", H(runs["split"][0]))):
+        ref = oracle.accel_targets(pos, s.mass, s.G, idx)
+        e64 = rel(H(nb.accel(T(pos), m, s.G))[:, idx], ref)
+        esp = rel(H(nb.accel(T(pos), m, s.G, precision="split"))[:, idx], ref)
+        log(f"n=131072 {label} state: sampled accel rel err fp64 {e64:.2e}, split {esp:.2e}")
+        assert e64 <= 1e-13 and esp <= 2e-12
+
+
+@pytest.mark.parametrize("k,steps", [(0, 3650), (1, 200), (1, 10000)])
 def test_split_energy_matches_fp64(k, steps):
     s = S.config(k)
     m = T(s.mass)
