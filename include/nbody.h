@@ -120,6 +120,24 @@ int32_t nbody_verlet_run(double* pos, double* vel, const double* mass,
                          int32_t precision, double small_mass,
                          void* workspace, size_t workspace_bytes, void* stream);
 
+/* nbody_verlet_run for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same run, bit for bit, with no workspace argument.  Its
+ * scratch memory (partials, G m, the second position buffer, the split
+ * form's class-ordered copies, the flags word) is a static 32 MiB device
+ * array that each GPU the library runs on holds until the process ends;
+ * its address is looked up once per device.  Runs whose scratch would
+ * exceed 32 MiB (about 20,000 bodies) return NBODY_EUNSUPPORTED with
+ * nothing enqueued.  Every launch is enqueued directly on `stream` (no
+ * captured graphs, which allocate), so a caller may itself capture the call;
+ * the call allocates nothing and frees nothing.  Calls on one GPU share its
+ * scratch: calls that overlap in time on that GPU (two streams, two host
+ * threads) race and must not be made.  The non-finite flag is cleared at
+ * the start of each call and not reported. */
+int32_t nbody_verlet_run_static(double* pos, double* vel, const double* mass,
+                                int64_t n, double G, double dt, int64_t steps,
+                                int32_t precision, double small_mass, void* stream);
+
 /* The classical fourth-order Runge-Kutta method, the higher-order
  * alternative to velocity Verlet that Sec. 2 names, for r' = v, v' = a(r)
  * with a from Eq. (1): advance (pos, vel) in place by `steps` steps of size

@@ -21,7 +21,8 @@ NBODY_FP64, NBODY_SPLIT, NBODY_SPLIT_COMPENSATED = 0, 1, 2
 OP_ACCEL, OP_RUN, OP_ADJOINT, OP_BATCHED, OP_ENERGY, OP_RK4 = range(6)
 
 EXPORTS = (
-    "nbody_workspace_bytes", "nbody_accel", "nbody_verlet_run", "nbody_rk4_run",
+    "nbody_workspace_bytes", "nbody_accel", "nbody_verlet_run", "nbody_verlet_run_static",
+    "nbody_rk4_run",
     "nbody_verlet_adjoint",
     "nbody_verlet_run_batched", "nbody_energy", "nbody_momenta", "nbody_get_flags",
     "nbody_get_tile", "nbody_set_tile", "nbody_autotune", "nbody_autotune_batched",
@@ -70,6 +71,8 @@ def load():
         lib.nbody_accel.argtypes = [_P, _P, _P, _I64, _D, _D, _I64, _P, _I32, _D, _P, _SZ, _P]
         lib.nbody_verlet_run.restype = _I32
         lib.nbody_verlet_run.argtypes = [_P, _P, _P, _I64, _D, _D, _I64, _I32, _D, _P, _SZ, _P]
+        lib.nbody_verlet_run_static.restype = _I32
+        lib.nbody_verlet_run_static.argtypes = [_P, _P, _P, _I64, _D, _D, _I64, _I32, _D, _P]
         lib.nbody_rk4_run.restype = _I32
         lib.nbody_rk4_run.argtypes = [_P, _P, _P, _I64, _D, _D, _I64, _I32, _D, _P, _SZ, _P]
         lib.nbody_verlet_adjoint.restype = _I32

@@ -773,6 +773,34 @@ int verlet_run_on(double* pos, double* vel, const double* mass, int64_t n, doubl
     return NBODY_OK;
 }
 
+// Scratch of nbody_verlet_run_static: one array per device, held until the
+// process ends.  Host code never uses the array's name as an address: the
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(void** out)
+{
+    int dev = 0;
+    NB_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(NBODY_EUNSUPPORTED, "device %d is beyond the library's %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(NBODY_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return NBODY_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -787,6 +815,27 @@ int32_t nbody_verlet_run(double* pos, double* vel, const double* mass, int64_t n
     NB_TRY(check_ws(workspace, workspace_bytes, L.total));
     return verlet_run_on(pos, vel, mass, n, G, dt, steps, precision, small_mass, workspace, L,
                          static_cast<hipStream_t>(stream), true);
+}
+
+int32_t nbody_verlet_run_static(double* pos, double* vel, const double* mass, int64_t n, double G,
+                                double dt, int64_t steps, int32_t precision, double small_mass,
+                                void* stream)
+{
+    g_err.clear();
+    NB_TRY(check_run(pos, vel, mass, n, G, dt, steps, precision, small_mass));
+    const Layout L = layout(NBODY_OP_RUN, n, 1, steps, 1, precision);
+    if (L.total > kStaticScratchBytes)
+        return fail(NBODY_EUNSUPPORTED,
+                    "n = %lld needs %zu bytes of scratch; the static scratch holds %zu "
+                    "(use nbody_verlet_run with a workspace)",
+                    (long long)n, L.total, kStaticScratchBytes);
+    if (steps == 0) return NBODY_OK;
+    void* ws = nullptr;
+    NB_TRY(static_scratch(&ws));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // the flags word starts each call at zero (a fill kernel, not a memset)
+    NB_HIP(launch_fill(at<double>(ws, L.flags), 0.0, 1, s));
+    return verlet_run_on(pos, vel, mass, n, G, dt, steps, precision, small_mass, ws, L, s, false);
 }
 
 int32_t nbody_rk4_run(double* pos, double* vel, const double* mass, int64_t n, double G,

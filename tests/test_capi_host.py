@@ -287,3 +287,18 @@ def test_compensated_split_form_host_rules():
         assert ws_bytes(op, 10425, 1, 0, 1, C.NBODY_SPLIT_COMPENSATED) == \
             ws_bytes(op, 10425, 1, 0, 1, C.NBODY_SPLIT) > 0
 
+def test_static_scratch_run_validates_first():
+    """nbody_verlet_run_static: bad arguments and runs whose scratch would
+    exceed the static array are refused before anything touches the device;
+    zero steps is a no-op."""
+    lib = _lib()
+    run = lib.nbody_verlet_run_static
+    assert run(FAKE, None, FAKE, 10, 1.0, 0.1, 5, 0, 0.0, None) == C.NBODY_EINVAL
+    assert run(FAKE, FAKE, FAKE, 10, 1.0, 0.1, -1, 0, 0.0, None) == C.NBODY_EINVAL
+    assert run(FAKE, FAKE, FAKE, 10, 1.0, 0.1, 5, 3, 0.0, None) == C.NBODY_EINVAL
+    assert run(FAKE, FAKE, FAKE, 10, float("inf"), 0.1, 5, 0, 0.0, None) == C.NBODY_EINVAL
+    for prec in (0, 1, 2):
+        assert run(FAKE, FAKE, FAKE, 40000, 1.0, 0.1, 5, prec, 0.0, None) == C.NBODY_EUNSUPPORTED
+        assert "static scratch" in C.last_error()
+    assert run(FAKE, FAKE, FAKE, 10, 1.0, 0.1, 0, 0, 0.0, None) == C.NBODY_OK
+
