@@ -509,7 +509,23 @@ def bench_adjoint(args, S, nb, torch, np, dev):
     gr, gv, gm, _, _ = nb.verlet_adjoint(*args_adj)
     torch.cuda.synchronize()
     t_adj = time.perf_counter() - t0
-    log(f"adjoint of {K} steps: {t_adj:.3f} s")
+    # the same gradient in two calls: the forward run keeping its checkpoints
+    # (what an autograd forward pass runs), then the reverse sweep alone
+    r0, v0 = args_adj[0], args_adj[1]
+    lam_r, lam_v = args_adj[7], args_adj[8]
+    _, _, ck = nb.verlet_checkpoints(r0, v0, m, G, dt, K, 100)
+    nb.verlet_adjoint_from_checkpoints(ck, m, G, dt, K, 100, lam_r, lam_v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, ck = nb.verlet_checkpoints(r0, v0, m, G, dt, K, 100)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    g2 = nb.verlet_adjoint_from_checkpoints(ck, m, G, dt, K, 100, lam_r, lam_v)
+    torch.cuda.synchronize()
+    t_rev = time.perf_counter() - t0 - t_fwd
+    same = all(torch.equal(x, y) for x, y in zip(g2, (gr, gv, gm)))
+    log(f"adjoint of {K} steps: {t_adj:.3f} s in one call; forward with checkpoints "
+        f"{t_fwd:.3f} s + reverse sweep {t_rev:.3f} s (bitwise equal: {same})")
     grad = np.concatenate([gr.cpu().numpy().ravel(), gv.cpu().numpy().ravel(),
                            gm.cpu().numpy()[1:31]])
     coords = S.fd_coordinates(s, args.fd_coords)
@@ -554,7 +570,8 @@ def bench_adjoint(args, S, nb, torch, np, dev):
     rel_l = np.abs(g - fl) / np.maximum(np.abs(fl), 1e-300)
     resolved = bd <= 1e-7 * np.abs(fs)
     out = {"metric": "adjoint vs central finite differences", "steps": K, "n": n,
-           "checkpoint_every": 100, "adjoint_s": t_adj, "coords": len(rows),
+           "checkpoint_every": 100, "adjoint_s": t_adj, "forward_with_checkpoints_s": t_fwd,
+           "reverse_sweep_s": t_rev, "split_calls_bitwise_equal": bool(same), "coords": len(rows),
            "rel_step": 1e-7, "rows": rows,
            "fd_state": {"pass_1e-6": int(((rel_s <= 1e-6) | ~big).sum()),
                         "resolved": int((resolved & big).sum()),

@@ -89,7 +89,10 @@ typedef enum {
     NBODY_OP_ADJOINT = 2,
     NBODY_OP_BATCHED = 3,
     NBODY_OP_ENERGY = 4,
-    NBODY_OP_RK4 = 5
+    NBODY_OP_RK4 = 5,
+    /* nbody_verlet_checkpoints and nbody_verlet_adjoint_from_checkpoints
+     * (the adjoint's workspace without its checkpoints) */
+    NBODY_OP_ADJOINT_SWEEP = 6
 } nbody_op;
 
 /* Bytes of workspace that `op` needs.  n_total: bodies (for BATCHED, the sum
@@ -171,6 +174,31 @@ int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const doubl
                              double* grad_pos0, double* grad_vel0, double* grad_mass,
                              double* pos_out, double* vel_out,
                              void* workspace, size_t workspace_bytes, void* stream);
+
+/* The two halves of nbody_verlet_adjoint, for callers that run the forward
+ * trajectory anyway (an autograd forward pass) and take its gradient later:
+ * nbody_verlet_checkpoints runs the FP64 forward run of nbody_verlet_adjoint
+ * from (pos0, vel0), storing (r, v) at steps 0, K, 2K, ... and at `steps`
+ * into `checkpoints` (a DEVICE buffer of (ceil(steps / K) + 1) * 6n doubles,
+ * record k = r_kK in doubles [6nk, 6nk + 3n) and v_kK in the next 3n; the
+ * last record holds the final state) and the final state into pos_out /
+ * vel_out (may be NULL); nbody_verlet_adjoint_from_checkpoints runs the
+ * reverse sweep of nbody_verlet_adjoint from such a buffer (unchanged, and
+ * the same n, G, dt, steps, K and masses).  Their results equal
+ * nbody_verlet_adjoint's bit for bit.  Workspace: nbody_workspace_bytes with
+ * op NBODY_OP_ADJOINT_SWEEP.  K = checkpoint_every >= 1. */
+int32_t nbody_verlet_checkpoints(const double* pos0, const double* vel0, const double* mass,
+                                 int64_t n, double G, double dt, int64_t steps,
+                                 int64_t checkpoint_every, double* checkpoints,
+                                 double* pos_out, double* vel_out,
+                                 void* workspace, size_t workspace_bytes, void* stream);
+int32_t nbody_verlet_adjoint_from_checkpoints(const double* checkpoints, const double* mass,
+                                              int64_t n, double G, double dt, int64_t steps,
+                                              int64_t checkpoint_every,
+                                              const double* grad_posT, const double* grad_velT,
+                                              double* grad_pos0, double* grad_vel0,
+                                              double* grad_mass, void* workspace,
+                                              size_t workspace_bytes, void* stream);
 
 /* Eqs. (3)-(4) for num_systems independent systems in one launch per step.
  * System k owns bodies [offsets_host[k], offsets_host[k+1]) of the

@@ -1,9 +1,11 @@
 """torch.autograd.Function for a whole velocity-Verlet trajectory.
 
-Forward runs Eqs. (3)-(4) on the GPU; backward calls the library's discrete
-adjoint (reverse sweep with checkpoint-and-recompute every K steps), which
-returns the exact gradient of the discrete trajectory with respect to the
-initial positions, velocities and the masses.
+Forward runs Eqs. (3)-(4) on the GPU and keeps the run's checkpoints (r, v)
+every K steps; backward runs the library's discrete adjoint from those
+checkpoints (reverse sweep, recomputing each K-step segment), which returns
+the exact gradient of the discrete trajectory with respect to the initial
+positions, velocities and the masses.  The forward trajectory is computed
+once.
 """
 from __future__ import annotations
 
@@ -17,23 +19,22 @@ class VerletRun(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, r0, v0, m, G, dt, steps, checkpoint_every=100):
-        r = r0.detach().clone().contiguous()
-        v = v0.detach().clone().contiguous()
         md = m.detach().contiguous()
-        nbody.verlet_run(r, v, md, G, dt, steps, "fp64")
-        ctx.save_for_backward(r0.detach(), v0.detach(), md)
+        r, v, ck = nbody.verlet_checkpoints(r0.detach().contiguous(), v0.detach().contiguous(),
+                                            md, G, dt, steps, checkpoint_every)
+        ctx.save_for_backward(ck, md)
         ctx.G, ctx.dt, ctx.steps, ctx.K = float(G), float(dt), int(steps), int(checkpoint_every)
         return r, v
 
     @staticmethod
     def backward(ctx, grad_r, grad_v):
-        r0, v0, m = ctx.saved_tensors
+        ck, m = ctx.saved_tensors
         if grad_r is None:
-            grad_r = torch.zeros_like(r0)
+            grad_r = torch.zeros((3, m.shape[0]), dtype=m.dtype, device=m.device)
         if grad_v is None:
-            grad_v = torch.zeros_like(v0)
-        gr, gv, gm, _, _ = nbody.verlet_adjoint(r0, v0, m, ctx.G, ctx.dt, ctx.steps, ctx.K,
-                                                grad_r.contiguous(), grad_v.contiguous())
+            grad_v = torch.zeros((3, m.shape[0]), dtype=m.dtype, device=m.device)
+        gr, gv, gm = nbody.verlet_adjoint_from_checkpoints(ck, m, ctx.G, ctx.dt, ctx.steps, ctx.K,
+                                                           grad_r.contiguous(), grad_v.contiguous())
         return gr, gv, gm, None, None, None, None
 
 

@@ -206,11 +206,12 @@ Layout layout(int op, int64_t n, int32_t ns, int64_t steps, int64_t K, int prec)
     const int cap = op == NBODY_OP_BATCHED ? kBatchSlots
                   : op == NBODY_OP_ENERGY  ? chunk_cap(n)
                                            : part_slots(n);
-    const int planes = (op == NBODY_OP_ADJOINT) ? 4 : 3;
+    const bool adj = op == NBODY_OP_ADJOINT || op == NBODY_OP_ADJOINT_SWEEP;
+    const int planes = adj ? 4 : 3;
     L.part = a.take((size_t)cap * planes * n * d);
     L.alt = a.take(3 * n * d);
     L.gm = a.take(n * d);
-    if (prec != NBODY_FP64 && op != NBODY_OP_ADJOINT && op != NBODY_OP_ENERGY) {
+    if (prec != NBODY_FP64 && !adj && op != NBODY_OP_ENERGY) {
         L.perm = a.take(n * sizeof(int32_t));
         L.nmaj = a.take((size_t)ns * sizeof(int64_t));
         L.offs = a.take((size_t)(ns + 1) * sizeof(int64_t));
@@ -233,9 +234,11 @@ Layout layout(int op, int64_t n, int32_t ns, int64_t steps, int64_t K, int prec)
         L.units = a.take((size_t)max_units * sizeof(BatchUnit));
         L.bchunks = a.take(n);
     }
-    if (op == NBODY_OP_ADJOINT) {
+    if (adj) {
         const int64_t nck = (steps + K - 1) / K;
-        L.ck = a.take((size_t)(nck + 1) * 6 * n * d);
+        // the checkpoints: in the workspace for NBODY_OP_ADJOINT, in the
+        // caller's buffer for the split forward and reverse calls
+        if (op == NBODY_OP_ADJOINT) L.ck = a.take((size_t)(nck + 1) * 6 * n * d);
         L.seg = a.take((size_t)std::min(K, std::max<int64_t>(steps, 1)) * 3 * n * d);
         // the next segment's positions, recomputed on a second stream while the
         // reverse sweep works on this one, with that stream's partials and velocity
@@ -616,11 +619,13 @@ size_t nbody_workspace_bytes(int32_t op, int64_t n_total, int32_t num_systems, i
                              int64_t checkpoint_every, int32_t precision)
 {
     if (n_total < 1 || n_total > kMaxBodies || num_systems < 1) return 0;
-    if (op < NBODY_OP_ACCEL || op > NBODY_OP_RK4) return 0;
+    if (op < NBODY_OP_ACCEL || op > NBODY_OP_ADJOINT_SWEEP) return 0;
     if (precision != NBODY_FP64 && precision != NBODY_SPLIT &&
         precision != NBODY_SPLIT_COMPENSATED)
         return 0;
-    if (op == NBODY_OP_ADJOINT && (checkpoint_every < 1 || steps < 0)) return 0;
+    if ((op == NBODY_OP_ADJOINT || op == NBODY_OP_ADJOINT_SWEEP) &&
+        (checkpoint_every < 1 || steps < 0))
+        return 0;
     return layout(op, n_total, num_systems, steps, checkpoint_every, precision).total;
 }
 
@@ -978,27 +983,19 @@ void nbody_reset_caches(void)
     drop_batch_plans();
 }
 
-int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const double* mass, int64_t n,
-                             double G, double dt, int64_t steps, int64_t checkpoint_every,
-                             const double* grad_posT, const double* grad_velT, double* grad_pos0,
-                             double* grad_vel0, double* grad_mass, double* pos_out,
-                             double* vel_out, void* workspace, size_t workspace_bytes,
-                             void* stream)
+// The adjoint's forward run (checkpoints (r, v) every K steps into ck, the
+// final state into pos_out / vel_out) and/or its reverse sweep from those
+// checkpoints, on a workspace laid out as L.  Arguments are checked.
+static int adjoint_core(const double* pos0, const double* vel0, const double* mass, int64_t n,
+                        double G, double dt, int64_t steps, int64_t checkpoint_every, double* ck,
+                        bool forward, bool reverse, const double* grad_posT,
+                        const double* grad_velT, double* grad_pos0, double* grad_vel0,
+                        double* grad_mass, double* pos_out, double* vel_out, void* workspace,
+                        const Layout& L, hipStream_t s)
 {
-    g_err.clear();
-    NB_TRY(check_common(pos0, mass, n, G));
-    if (!vel0 || !grad_posT || !grad_velT || !grad_pos0 || !grad_vel0 || !grad_mass)
-        return fail(NBODY_EINVAL, "null velocity, cotangent or gradient pointer");
-    if (steps < 0) return fail(NBODY_EINVAL, "steps must be >= 0");
-    if (checkpoint_every < 1) return fail(NBODY_EINVAL, "checkpoint_every must be >= 1");
-    if (!std::isfinite(dt)) return fail(NBODY_EINVAL, "dt is not finite");
-    const Layout L = layout(NBODY_OP_ADJOINT, n, 1, steps, checkpoint_every, NBODY_FP64);
-    NB_TRY(check_ws(workspace, workspace_bytes, L.total));
-    hipStream_t s = static_cast<hipStream_t>(stream);
     const size_t b3 = 3 * n * sizeof(double);
     const int64_t K = checkpoint_every;
     const int64_t nck = (steps + K - 1) / K;
-    double* ck = at<double>(workspace, L.ck);
     double* seg = at<double>(workspace, L.seg);
     double* alt = at<double>(workspace, L.alt);
     double* lam_r = at<double>(workspace, L.lam_r);
@@ -1065,31 +1062,34 @@ int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const doubl
         return maybe_graph_on(s, key, kseg, body);
     };
     NB_HIP(launch_scale(mass, G, n, gm, s));
-    NB_HIP(hipMemcpyAsync(ck_r(0), pos0, b3, hipMemcpyDeviceToDevice, s));
-    NB_HIP(hipMemcpyAsync(ck_v(0), vel0, b3, hipMemcpyDeviceToDevice, s));
-    for (int64_t c = 0; c < nck; ++c) {
-        const int64_t kseg = std::min(K, steps - c * K);
-        NB_HIP(hipMemcpyAsync(w0, ck_r(c), b3, hipMemcpyDeviceToDevice, s));
-        NB_HIP(hipMemcpyAsync(wv, ck_v(c), b3, hipMemcpyDeviceToDevice, s));
-        const double* r_end = w0;
-        if (small) {
-            NB_HIP(launch_run_small(0, P.tile, w0, w0, wv, mass, n, nullptr, G, dt, 0, kseg, kseg,
-                                    nullptr, nullptr, flags, s));
-        } else {
-            NB_TRY(maybe_graph(key_of(2, kseg, 0, seg), kseg, [&](hipStream_t cs) {
-                for (int64_t i = 0; i <= kseg; ++i) {
-                    const int st = step_launch(P, i, kseg, cs);
-                    if (st != NBODY_OK) return st;
-                }
-                return (int)NBODY_OK;
-            }));
-            r_end = P.buf[kseg & 1];
+    if (forward) {
+        NB_HIP(hipMemcpyAsync(ck_r(0), pos0, b3, hipMemcpyDeviceToDevice, s));
+        NB_HIP(hipMemcpyAsync(ck_v(0), vel0, b3, hipMemcpyDeviceToDevice, s));
+        for (int64_t c = 0; c < nck; ++c) {
+            const int64_t kseg = std::min(K, steps - c * K);
+            NB_HIP(hipMemcpyAsync(w0, ck_r(c), b3, hipMemcpyDeviceToDevice, s));
+            NB_HIP(hipMemcpyAsync(wv, ck_v(c), b3, hipMemcpyDeviceToDevice, s));
+            const double* r_end = w0;
+            if (small) {
+                NB_HIP(launch_run_small(0, P.tile, w0, w0, wv, mass, n, nullptr, G, dt, 0, kseg, kseg,
+                                        nullptr, nullptr, flags, s));
+            } else {
+                NB_TRY(maybe_graph(key_of(2, kseg, 0, seg), kseg, [&](hipStream_t cs) {
+                    for (int64_t i = 0; i <= kseg; ++i) {
+                        const int st = step_launch(P, i, kseg, cs);
+                        if (st != NBODY_OK) return st;
+                    }
+                    return (int)NBODY_OK;
+                }));
+                r_end = P.buf[kseg & 1];
+            }
+            NB_HIP(hipMemcpyAsync(ck_r(c + 1), r_end, b3, hipMemcpyDeviceToDevice, s));
+            NB_HIP(hipMemcpyAsync(ck_v(c + 1), wv, b3, hipMemcpyDeviceToDevice, s));
         }
-        NB_HIP(hipMemcpyAsync(ck_r(c + 1), r_end, b3, hipMemcpyDeviceToDevice, s));
-        NB_HIP(hipMemcpyAsync(ck_v(c + 1), wv, b3, hipMemcpyDeviceToDevice, s));
+        if (pos_out) NB_HIP(hipMemcpyAsync(pos_out, ck_r(nck), b3, hipMemcpyDeviceToDevice, s));
+        if (vel_out) NB_HIP(hipMemcpyAsync(vel_out, ck_v(nck), b3, hipMemcpyDeviceToDevice, s));
     }
-    if (pos_out) NB_HIP(hipMemcpyAsync(pos_out, ck_r(nck), b3, hipMemcpyDeviceToDevice, s));
-    if (vel_out) NB_HIP(hipMemcpyAsync(vel_out, ck_v(nck), b3, hipMemcpyDeviceToDevice, s));
+    if (!reverse) return NBODY_OK;
 
     // Reverse sweep: one transpose-Jacobian product of Eq. (1) per force
     // pass, its chunk reduction fused with the adjoint of the drift that
@@ -1169,6 +1169,74 @@ int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const doubl
     NB_HIP(hipMemcpyAsync(grad_vel0, lam_v, b3, hipMemcpyDeviceToDevice, s));
     NB_HIP(hipMemcpyAsync(grad_mass, g_m, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     return NBODY_OK;
+}
+
+static int check_adjoint(const double* pos0, const double* vel0, const double* mass, int64_t n,
+                         double G, double dt, int64_t steps, int64_t checkpoint_every)
+{
+    NB_TRY(check_common(pos0, mass, n, G));
+    if (!vel0) return fail(NBODY_EINVAL, "null velocity pointer");
+    if (steps < 0) return fail(NBODY_EINVAL, "steps must be >= 0");
+    if (checkpoint_every < 1) return fail(NBODY_EINVAL, "checkpoint_every must be >= 1");
+    if (!std::isfinite(dt)) return fail(NBODY_EINVAL, "dt is not finite");
+    return NBODY_OK;
+}
+
+int32_t nbody_verlet_adjoint(const double* pos0, const double* vel0, const double* mass, int64_t n,
+                             double G, double dt, int64_t steps, int64_t checkpoint_every,
+                             const double* grad_posT, const double* grad_velT, double* grad_pos0,
+                             double* grad_vel0, double* grad_mass, double* pos_out,
+                             double* vel_out, void* workspace, size_t workspace_bytes,
+                             void* stream)
+{
+    g_err.clear();
+    NB_TRY(check_adjoint(pos0, vel0, mass, n, G, dt, steps, checkpoint_every));
+    if (!grad_posT || !grad_velT || !grad_pos0 || !grad_vel0 || !grad_mass)
+        return fail(NBODY_EINVAL, "null cotangent or gradient pointer");
+    const Layout L = layout(NBODY_OP_ADJOINT, n, 1, steps, checkpoint_every, NBODY_FP64);
+    NB_TRY(check_ws(workspace, workspace_bytes, L.total));
+    return adjoint_core(pos0, vel0, mass, n, G, dt, steps, checkpoint_every,
+                        at<double>(workspace, L.ck), true, true, grad_posT, grad_velT, grad_pos0,
+                        grad_vel0, grad_mass, pos_out, vel_out, workspace, L,
+                        static_cast<hipStream_t>(stream));
+}
+
+int32_t nbody_verlet_checkpoints(const double* pos0, const double* vel0, const double* mass,
+                                 int64_t n, double G, double dt, int64_t steps,
+                                 int64_t checkpoint_every, double* checkpoints, double* pos_out,
+                                 double* vel_out, void* workspace, size_t workspace_bytes,
+                                 void* stream)
+{
+    g_err.clear();
+    NB_TRY(check_adjoint(pos0, vel0, mass, n, G, dt, steps, checkpoint_every));
+    if (!checkpoints) return fail(NBODY_EINVAL, "null checkpoint buffer");
+    const Layout L = layout(NBODY_OP_ADJOINT_SWEEP, n, 1, steps, checkpoint_every, NBODY_FP64);
+    NB_TRY(check_ws(workspace, workspace_bytes, L.total));
+    return adjoint_core(pos0, vel0, mass, n, G, dt, steps, checkpoint_every, checkpoints, true,
+                        false, nullptr, nullptr, nullptr, nullptr, nullptr, pos_out, vel_out,
+                        workspace, L, static_cast<hipStream_t>(stream));
+}
+
+int32_t nbody_verlet_adjoint_from_checkpoints(const double* checkpoints, const double* mass,
+                                              int64_t n, double G, double dt, int64_t steps,
+                                              int64_t checkpoint_every, const double* grad_posT,
+                                              const double* grad_velT, double* grad_pos0,
+                                              double* grad_vel0, double* grad_mass,
+                                              void* workspace, size_t workspace_bytes,
+                                              void* stream)
+{
+    g_err.clear();
+    if (!checkpoints) return fail(NBODY_EINVAL, "null checkpoint buffer");
+    NB_TRY(check_adjoint(checkpoints, checkpoints + 3 * n, mass, n, G, dt, steps,
+                         checkpoint_every));
+    if (!grad_posT || !grad_velT || !grad_pos0 || !grad_vel0 || !grad_mass)
+        return fail(NBODY_EINVAL, "null cotangent or gradient pointer");
+    const Layout L = layout(NBODY_OP_ADJOINT_SWEEP, n, 1, steps, checkpoint_every, NBODY_FP64);
+    NB_TRY(check_ws(workspace, workspace_bytes, L.total));
+    return adjoint_core(nullptr, nullptr, mass, n, G, dt, steps, checkpoint_every,
+                        const_cast<double*>(checkpoints), false, true, grad_posT, grad_velT,
+                        grad_pos0, grad_vel0, grad_mass, nullptr, nullptr, workspace, L,
+                        static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -151,6 +151,65 @@ def verlet_adjoint(pos0, vel0, mass, G, dt, steps, checkpoint_every, grad_posT, 
     return gr, gv, gm, pT, vT
 
 
+def checkpoint_shape(n, steps, checkpoint_every):
+    """Shape of the checkpoint tensor of verlet_checkpoints: one (r, v)
+    record every K steps plus the final state."""
+    K = int(checkpoint_every)
+    return ((int(steps) + K - 1) // K + 1, 6, int(n))
+
+
+def verlet_checkpoints(pos0, vel0, mass, G, dt, steps, checkpoint_every):
+    """The forward half of verlet_adjoint: runs ``steps`` FP64 steps from
+    (pos0, vel0) and returns (r_T, v_T, checkpoints), checkpoints a device
+    tensor of checkpoint_shape(...) for verlet_adjoint_from_checkpoints."""
+    n = _mass(mass)
+    _state(pos0, "pos0", n)
+    _state(vel0, "vel0", n)
+    dev = _same_device(pos0, vel0, mass)
+    steps, K = int(steps), int(checkpoint_every)
+    ck = torch.empty(checkpoint_shape(n, steps, max(K, 1)), dtype=torch.float64, device=dev)
+    pT = torch.empty((3, n), dtype=torch.float64, device=dev)
+    vT = torch.empty_like(pT)
+    lib = C.load()
+    ws = C.workspace(C.workspace_bytes(C.OP_ADJOINT_SWEEP, n, steps=steps,
+                                       checkpoint_every=max(K, 1)), dev)
+    st = lib.nbody_verlet_checkpoints(pos0.data_ptr(), vel0.data_ptr(), mass.data_ptr(), n,
+                                      float(G), float(dt), steps, K, ck.data_ptr(), pT.data_ptr(),
+                                      vT.data_ptr(), ws.data_ptr(), ws.numel(),
+                                      C.stream_handle(dev))
+    C.check(st, "nbody_verlet_checkpoints")
+    return pT, vT, ck
+
+
+def verlet_adjoint_from_checkpoints(checkpoints, mass, G, dt, steps, checkpoint_every,
+                                    grad_posT, grad_velT):
+    """The reverse half of verlet_adjoint: (dL/dr0, dL/dv0, dL/dm) from the
+    checkpoints of verlet_checkpoints (same masses, G, dt, steps, K)."""
+    n = _mass(mass)
+    steps, K = int(steps), int(checkpoint_every)
+    if not isinstance(checkpoints, torch.Tensor) or checkpoints.dtype != torch.float64 or \
+            tuple(checkpoints.shape) != checkpoint_shape(n, steps, max(K, 1)) or \
+            not checkpoints.is_contiguous() or checkpoints.device.type != "cuda":
+        raise ValueError("checkpoints must be the contiguous float64 GPU tensor of "
+                         "verlet_checkpoints for these sizes")
+    for t, name in ((grad_posT, "grad_posT"), (grad_velT, "grad_velT")):
+        _state(t, name, n)
+    dev = _same_device(checkpoints, mass, grad_posT, grad_velT)
+    gr = torch.empty((3, n), dtype=torch.float64, device=dev)
+    gv = torch.empty_like(gr)
+    gm = torch.empty((n,), dtype=torch.float64, device=dev)
+    lib = C.load()
+    ws = C.workspace(C.workspace_bytes(C.OP_ADJOINT_SWEEP, n, steps=steps,
+                                       checkpoint_every=max(K, 1)), dev)
+    st = lib.nbody_verlet_adjoint_from_checkpoints(checkpoints.data_ptr(), mass.data_ptr(), n,
+                                                   float(G), float(dt), steps, K,
+                                                   grad_posT.data_ptr(), grad_velT.data_ptr(),
+                                                   gr.data_ptr(), gv.data_ptr(), gm.data_ptr(),
+                                                   ws.data_ptr(), ws.numel(), C.stream_handle(dev))
+    C.check(st, "nbody_verlet_adjoint_from_checkpoints")
+    return gr, gv, gm
+
+
 def verlet_run_batched(pos, vel, mass, offsets, G, dt, steps, precision="fp64", small_mass=None):
     """Advances many independent systems (concatenated SoA, system k owns
     bodies offsets[k]:offsets[k+1]) in place."""

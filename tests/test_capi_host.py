@@ -287,6 +287,7 @@ def test_compensated_split_form_host_rules():
         assert ws_bytes(op, 10425, 1, 0, 1, C.NBODY_SPLIT_COMPENSATED) == \
             ws_bytes(op, 10425, 1, 0, 1, C.NBODY_SPLIT) > 0
 
+
 def test_static_scratch_run_validates_first():
     """nbody_verlet_run_static: bad arguments and runs whose scratch would
     exceed the static array are refused before anything touches the device;
@@ -302,3 +303,23 @@ def test_static_scratch_run_validates_first():
         assert "static scratch" in C.last_error()
     assert run(FAKE, FAKE, FAKE, 10, 1.0, 0.1, 0, 0, 0.0, None) == C.NBODY_OK
 
+
+def test_split_adjoint_validates_first():
+    lib = _lib()
+    ws = ctypes.c_void_p(0x100000)
+    big = 1 << 40
+    ck = lib.nbody_verlet_checkpoints
+    rev = lib.nbody_verlet_adjoint_from_checkpoints
+    assert ck(FAKE, FAKE, FAKE, 10, 1.0, 0.1, 5, 2, None, None, None, ws, big, None) == C.NBODY_EINVAL
+    assert ck(FAKE, None, FAKE, 10, 1.0, 0.1, 5, 2, FAKE, None, None, ws, big, None) == C.NBODY_EINVAL
+    assert ck(FAKE, FAKE, FAKE, 10, 1.0, 0.1, 5, 0, FAKE, None, None, ws, big, None) == C.NBODY_EINVAL
+    assert ck(FAKE, FAKE, FAKE, 10, 1.0, 0.1, 5, 2, FAKE, None, None, ws, 64, None) == C.NBODY_EWORKSPACE
+    assert rev(None, FAKE, 10, 1.0, 0.1, 5, 2, FAKE, FAKE, FAKE, FAKE, FAKE, ws, big, None) == C.NBODY_EINVAL
+    assert rev(FAKE, FAKE, 10, 1.0, 0.1, 5, 2, None, FAKE, FAKE, FAKE, FAKE, ws, big, None) == C.NBODY_EINVAL
+    assert rev(FAKE, FAKE, 10, 1.0, 0.1, -1, 2, FAKE, FAKE, FAKE, FAKE, FAKE, ws, big, None) == C.NBODY_EINVAL
+    wsb = lib.nbody_workspace_bytes
+    # the sweep's workspace is the adjoint's without its checkpoints
+    full = wsb(C.OP_ADJOINT, 2079, 1, 36500, 100, 0)
+    sweep = wsb(C.OP_ADJOINT_SWEEP, 2079, 1, 36500, 100, 0)
+    assert 0 < sweep < full and full - sweep >= 366 * 6 * 2079 * 8
+    assert wsb(C.OP_ADJOINT_SWEEP, 10, 1, 5, 0, 0) == 0

@@ -272,3 +272,29 @@ def test_autograd_function():
     assert torch.equal(r0.grad, Gr) and torch.equal(v0.grad, Gv) and torch.equal(m.grad, Gm)
     gr, gv, gm = oracle.adjoint(s.pos, s.vel, s.mass, s.G, 0.1, 120, H(w), H(2 * vT.detach()))
     assert nrel(H(r0.grad), gr) <= 1e-10 and nrel(H(m.grad), gm) <= 1e-10
+
+
+@pytest.mark.parametrize("steps,K", [(120, 11), (100, 100), (7, 3), (0, 5)])
+def test_checkpoints_then_reverse_equals_adjoint(steps, K):
+    """nbody_verlet_checkpoints followed by nbody_verlet_adjoint_from_checkpoints
+    gives nbody_verlet_adjoint's gradients and final state bit for bit, and
+    the checkpoints are the plain run's states (record k = state after kK
+    steps, the last one the final state)."""
+    nb.reset_caches()
+    s = S.config(4) if steps >= 100 else S.solar_system(44, 300, n_major=30)
+    rng = np.random.default_rng(steps + K)
+    lr, lv = T(rng.normal(size=(3, s.n))), T(rng.normal(size=(3, s.n)))
+    r, v, m = T(s.pos), T(s.vel), T(s.mass)
+    want = [H(x) for x in nb.verlet_adjoint(r, v, m, s.G, s.dt, steps, K, lr, lv)]
+    pT, vT, ck = nb.verlet_checkpoints(r, v, m, s.G, s.dt, steps, K)
+    got = [H(x) for x in nb.verlet_adjoint_from_checkpoints(ck, m, s.G, s.dt, steps, K, lr, lv)]
+    for a, b in zip(got, want[:3]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(H(pT), want[3]) and np.array_equal(H(vT), want[4])
+    C = H(ck)
+    assert C.shape == ((steps + K - 1) // K + 1, 6, s.n)
+    for k in range(C.shape[0]):
+        p, vv = T(s.pos), T(s.vel)
+        nb.verlet_run(p, vv, m, s.G, s.dt, min(k * K, steps))
+        assert np.array_equal(C[k, :3], H(p)) and np.array_equal(C[k, 3:], H(vv))
+    assert np.array_equal(H(r), s.pos) and np.array_equal(H(v), s.vel)
