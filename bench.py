@@ -105,29 +105,46 @@ def read_traffic(kernel_key, tile):
         return None
 
 
-def counter_fractions(kernel_key, tile, ms):
-    """FP64 and FP32 vector FLOP/s of the force kernel as fractions of the
-    chip's peaks: counter flops per launch (rocprofv3 --pmc, FLOPs =
-    64 (ADD + MUL + TRANS + 2 FMA) per precision) from the committed summary
-    profiles/<kernel_key>_counters.txt taken with this tile, over the launch
-    time measured now (ms).  None if no such summary exists."""
+def counter_fractions(kernel_key, tile, ms, alg_flops):
+    """The force kernel's fraction of peak taken apart, from committed
+    rocprofv3 summaries taken with this tile and the launch time measured
+    now (ms):
+      counter_frac_fp64 / _fp32: FP64 / FP32 vector FLOP/s by the counters
+        (64 (ADD + MUL + TRANS + 2 FMA) per launch,
+        profiles/<kernel_key>_counters.txt) over the chip's peaks;
+      sclk_sustained_ghz: the shader clock held while the kernel runs
+        back to back (profiles/sclk_<kernel_key>.txt); the nominal peak
+        assumes 2.4 GHz;
+      issue_efficiency: the kernel's VALU work (SQ_ACTIVE_INST_VALU: busy
+        quad-cycles, spread evenly over the 1024 SIMDs) at the sustained
+        clock, over the launch time;
+      mix_efficiency: algorithmic flops (20 N (N - 1)) over the flops that
+        those VALU quad-cycles could issue at 128 per SIMD quad-cycle (one
+        FP64 FMA per lane);
+    so that frac = (sclk / 2.4) * issue_efficiency * mix_efficiency.
+    None where no summary matches."""
     vals = read_profile(f"{kernel_key}_counters", tile)
     if not vals:
         return None
     try:
         f64 = float(vals["fp64_flops_per_launch"])
         f32 = float(vals["fp32_flops_per_launch"])
+        quad = float(vals["SQ_ACTIVE_INST_VALU"])
     except (KeyError, ValueError):
         return None
     s = ms * 1e-3
     out = {"counter_frac_fp64": round(f64 / s / 1e12 / FP64_PEAK_TFLOPS, 4),
            "counter_frac_fp32": round(f32 / s / 1e12 / FP32_PEAK_TFLOPS, 4)}
-    for k in ("sclk_ghz", "valu_busy", "valu_issue_frac_of_sclk"):
-        if k in vals:
-            try:
-                out[k] = float(vals[k])
-            except ValueError:
-                pass
+    clk = read_profile(f"sclk_{kernel_key}", tile)
+    if clk and "sclk_sustained_ghz" in clk:
+        ghz = float(clk["sclk_sustained_ghz"])
+        issue_s = quad / 1024 * 4 / (ghz * 1e9)
+        out.update({"sclk_sustained_ghz": ghz,
+                    "clock_frac": round(ghz / 2.4, 4),
+                    "frac_of_sustained_clock_peak": round(
+                        alg_flops / s / 1e12 / (FP64_PEAK_TFLOPS * ghz / 2.4), 4),
+                    "issue_efficiency": round(issue_s / s, 4),
+                    "mix_efficiency": round(alg_flops / (quad * 128), 4)})
     return out
 
 
@@ -335,7 +352,7 @@ def roofline(n, tile, ms64, mssp):
         a = own / (ms64 * 1e-3) / 1e12
         roof["own_arithmetic"] = {"flops_per_launch": own, "achieved": round(a, 3),
                                   "frac": round(a / FP64_PEAK_TFLOPS, 4)}
-    cf = counter_fractions(f"force_fp64_n{n}", tile, ms64)
+    cf = counter_fractions(f"force_fp64_n{n}", tile, ms64, flops)
     if cf:
         roof.update(cf)
     return roof

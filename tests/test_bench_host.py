@@ -29,3 +29,23 @@ def test_traffic_only_for_the_profiled_tile():
     assert t is not None and t > 32 * 10425        # at least the source reads
     assert bench.read_traffic("force_fp64_n10425", dict(tile, variant=1)) is None
     assert bench.read_traffic("no_such_profile", tile) is None
+
+
+def test_roofline_counts_twenty_flops_per_ordered_pair():
+    """frac = 20 N (N - 1) per launch / launch time / 78.6 TFLOP/s, for the
+    each-pair-once kernel too (its own 27-flop arithmetic beside it); the
+    counter fractions and the clock / issue / mix decomposition come from
+    the committed summaries taken with the same tile, and multiply back to
+    the fraction."""
+    tile = {"targets_per_lane": 4, "waves": 4, "chunks": 1, "variant": 5}
+    n, ms = 10425, 0.0485
+    r = bench.roofline(n, tile, ms, 0.038)
+    want = 20 * n * (n - 1) / (ms * 1e-3) / 1e12
+    assert abs(r["achieved"] - round(want, 3)) < 1e-9 and abs(r["frac"] - round(want / 78.6, 4)) < 1e-9
+    assert r["own_arithmetic"]["flops_per_launch"] == 27 * n * (n - 1) // 2
+    assert 0.3 < r["counter_frac_fp64"] < 0.6 and r["counter_frac_fp32"] == 0.0
+    prod = r["clock_frac"] * r["issue_efficiency"] * r["mix_efficiency"]
+    assert abs(prod - r["frac"]) < 2e-3
+    # another tile: no counter figures
+    r1 = bench.roofline(n, dict(tile, variant=1), ms, 0.038)
+    assert "counter_frac_fp64" not in r1 and r1["traffic"] is None
