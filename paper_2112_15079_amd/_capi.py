@@ -132,19 +132,26 @@ def stream_handle(device=None) -> int:
 
 
 # ----------------------------------------------------------------------------
-# workspace: one growing, zero-initialised buffer per device
+# workspace: one growing, zero-initialised buffer per (device, stream)
 
 _ws = {}
 
 
 def workspace(nbytes: int, device) -> torch.Tensor:
-    """A 256-byte-aligned device buffer of at least nbytes (shared per device;
-    calls that use it are ordered on the current stream)."""
+    """A 256-byte-aligned device buffer of at least nbytes, one per (device,
+    current stream): calls on one stream are ordered and share it, calls on
+    different streams get different buffers and do not race.  A buffer that
+    grows is replaced; the old one goes back to torch's allocator in the
+    order of its stream's work, the only stream that used it (the library's
+    own second stream in the adjoint is ordered before the caller's stream
+    returns)."""
     dev = torch.device(device)
-    key = dev.index if dev.index is not None else torch.cuda.current_device()
+    index = dev.index if dev.index is not None else torch.cuda.current_device()
+    key = (index, torch.cuda.current_stream(index).cuda_stream)
     buf = _ws.get(key)
     if buf is None or buf.numel() < nbytes:
-        buf = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=dev)
+        with torch.cuda.device(index):
+            buf = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=dev)
         if buf.data_ptr() % 256:
             raise NBodyError("device allocation is not 256-byte aligned")
         _ws[key] = buf

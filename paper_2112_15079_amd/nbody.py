@@ -263,8 +263,9 @@ def momenta(pos, vel, mass):
 
 
 def get_flags(device=None, clear=False) -> int:
-    """Flags of the last runs on this device's shared workspace (bit 0:
-    non-finite value produced).  Synchronises the current stream."""
+    """Flags of the last runs on this device and the current stream (their
+    shared workspace; bit 0: non-finite value produced).  Synchronises the
+    current stream."""
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     ws = C.workspace(256, dev)
     v = ctypes.c_int32(0)

@@ -406,6 +406,30 @@ def test_graph_cache_eviction():
     assert rel(outs[0], pr) <= 1e-12
 
 
+def test_runs_on_two_streams_use_separate_workspaces():
+    """Calls made on two streams at once get a workspace each from the
+    binding (device, stream): two overlapping runs of different systems give
+    the same bits as each run made alone."""
+    a = S.solar_system(71, 2969, n_major=30)
+    b = S.solar_system(72, 5969, n_major=30)
+    want = []
+    for x in (a, b):
+        p, v = T(x.pos), T(x.vel)
+        nb.verlet_run(p, v, T(x.mass), x.G, 0.1, 150)
+        want.append((H(p), H(v)))
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    bufs = []
+    torch.cuda.synchronize()
+    for st, x in ((s1, a), (s2, b)):
+        with torch.cuda.stream(st):
+            p, v, m = T(x.pos), T(x.vel), T(x.mass)
+            nb.verlet_run(p, v, m, x.G, 0.1, 150)
+            bufs.append((p, v, m))
+    torch.cuda.synchronize()
+    for (p, v, _), (wp, wv) in zip(bufs, want):
+        assert np.array_equal(H(p), wp) and np.array_equal(H(v), wv)
+
+
 def test_verlet_zero_steps_is_noop():
     s = S.config(0)
     p, v = T(s.pos), T(s.vel)
