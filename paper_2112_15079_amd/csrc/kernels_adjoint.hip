@@ -11,6 +11,7 @@
 // one all-pairs pass over (r, m, u) with the same tiling as the force pass.
 #include "common.hpp"
 #include "pair_math.hpp"
+#include "reduce.hpp"
 
 namespace nb {
 namespace {
@@ -247,11 +248,8 @@ constexpr int kBlock = 256;
 // lam_r += sum of the chunk partials of planes 0..2, g_m += plane 3; then,
 // when `drift` is set, the adjoint of the drift that precedes this force pass
 // in the reverse sweep: lam_v += dt lam_r.  GS threads per (plane, body)
-// element: thread `sub` adds chunks sub, sub + GS, ... in ascending order with
-// its loads batched, and lane 0 of the group adds the GS sub-sums in order
-// (fixed order: deterministic).
-constexpr int kLoadBatch = 8;
-
+// element sum the partials in a fixed order (chunk_sum: deterministic); the
+// values the update reads are loaded before the partials.
 template <int GS>
 __global__ __launch_bounds__(kBlock) void k_vjp_reduce(const double* __restrict__ part,
                                                        int chunks, int64_t n,
@@ -265,38 +263,25 @@ __global__ __launch_bounds__(kBlock) void k_vjp_reduce(const double* __restrict_
     const int sub = (int)(t % GS);
     const bool live = i < 4 * n;
     const int64_t ii = live ? i : 0;
-    const int64_t stride = 4 * n;
-    double a = 0.0;
-    if (live) {
-        for (int c0 = sub; c0 < chunks; c0 += GS * kLoadBatch) {
-            double v[kLoadBatch];
-#pragma unroll
-            for (int u = 0; u < kLoadBatch; ++u) {
-                const int c = c0 + u * GS;
-                v[u] = (c < chunks) ? part[(int64_t)c * stride + ii] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < kLoadBatch; ++u)
-                if (c0 + u * GS < chunks) a += v[u];
+    const bool head = live && sub == 0;
+    const bool plane_r = i < 3 * n;
+    double r0 = 0.0, v0 = 0.0, m0 = 0.0;
+    if (head) {
+        if (plane_r) {
+            r0 = lam_r[i];
+            if (drift) v0 = lam_v[i];
+        } else {
+            m0 = g_m[i - 3 * n];
         }
     }
-    if (GS > 1) {
-        double total = a;
-        const int lane = threadIdx.x & 63;
-#pragma unroll
-        for (int g = 1; g < GS; ++g) {
-            const double o = __shfl(a, lane + g, 64);
-            if (sub == 0) total += o;
-        }
-        a = total;
-    }
-    if (!live || sub != 0) return;
-    if (i < 3 * n) {
-        const double r = lam_r[i] + a;
+    const double a = chunk_sum<GS>(part, chunks, 4 * n, ii, sub, live);
+    if (!head) return;
+    if (plane_r) {
+        const double r = r0 + a;
         lam_r[i] = r;
-        if (drift) lam_v[i] = __builtin_fma(dt, r, lam_v[i]);
+        if (drift) lam_v[i] = __builtin_fma(dt, r, v0);
     } else {
-        g_m[i - 3 * n] += a;
+        g_m[i - 3 * n] = m0 + a;
     }
 }
 

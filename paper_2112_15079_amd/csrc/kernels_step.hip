@@ -3,6 +3,7 @@
 // and the diagnostics of Sec. 2 (energy, momenta).
 #include "common.hpp"
 #include "pair_math.hpp"
+#include "reduce.hpp"
 
 namespace nb {
 namespace {
@@ -17,13 +18,12 @@ constexpr int kBlock = 256;
 //   kOpen:  v += dt/2 a;  r_out = r_in + dt v   (v_{i+3/2}, r_{i+2})
 // Eqs. (3)-(4) follow: r_{i+1} = r_i + dt (v_i + dt/2 a_i) and
 // v_{i+1} = v_i + dt/2 a_i + dt/2 a_{i+1}.
-// GS threads per (body, component): thread `sub` of a group adds chunks
-// sub, sub + GS, ... in ascending order with its loads batched, then lane 0
-// of the group adds the GS sub-sums in sub order.  The order is fixed, so the
-// result is deterministic, and the loads of all groups overlap.
-constexpr int kLoadBatch = 8;
-
-template <int GS>
+// GS threads per (body, component) sum the partials (chunk_sum); the state
+// the epilogue reads is loaded before the partials, so its latency overlaps
+// theirs.
+// PER_BODY: an ensemble's per-body partial counts (body_chunks) instead of
+// one count for every body.
+template <int GS, bool PER_BODY>
 __global__ __launch_bounds__(kBlock) void k_step(const double* __restrict__ part, int chunks,
                                                  const int8_t* __restrict__ body_chunks,
                                                  int64_t n, double* __restrict__ vel,
@@ -38,41 +38,20 @@ __global__ __launch_bounds__(kBlock) void k_step(const double* __restrict__ part
     const bool live = i < 3 * n;
     const int64_t ii = live ? i : 0;
     const int64_t p = ii % n;
-    const int C = body_chunks ? (int)body_chunks[p] : chunks;
-    const int64_t stride = 3 * n;
-    double a = 0.0;
-    if (live) {
-        for (int c0 = sub; c0 < C; c0 += GS * kLoadBatch) {
-            double v[kLoadBatch];
-#pragma unroll
-            for (int u = 0; u < kLoadBatch; ++u) {
-                const int c = c0 + u * GS;
-                v[u] = (c < C) ? part[(int64_t)c * stride + ii] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < kLoadBatch; ++u)
-                if (c0 + u * GS < C) a += v[u];
-        }
-    }
-    if (GS > 1) {
-        double total = a;
-        const int lane = threadIdx.x & 63;
-#pragma unroll
-        for (int g = 1; g < GS; ++g) {
-            const double o = __shfl(a, lane + g, 64);
-            if (sub == 0) total += o;
-        }
-        a = total;
-    }
-    if (!live || sub != 0) return;
+    const int C = PER_BODY ? (int)body_chunks[p] : chunks;
+    const bool head = live && sub == 0;
+    const double v0 = (head && (mode & (kClose | kOpen))) ? vel[i] : 0.0;
+    const double r0 = (head && (mode & kOpen)) ? pos_in[i] : 0.0;
+    const double a = chunk_sum<GS>(part, C, 3 * n, ii, sub, live);
+    if (!head) return;
     bool finite = __builtin_isfinite(a);
     if (mode & kStoreAcc) acc[i] = a;
     if (mode & (kClose | kOpen)) {
-        double v = vel[i];
+        double v = v0;
         if (mode & kClose) v = v + hdt * a;
         if (mode & kOpen) {
             v = v + hdt * a;
-            const double r = pos_in[i] + dt * v;
+            const double r = r0 + dt * v;
             finite = finite && __builtin_isfinite(r);
             pos_out[i] = r;
         }
@@ -106,52 +85,39 @@ __global__ __launch_bounds__(kBlock) void k_rk4_stage(const double* __restrict__
     const int sub = (int)(t % GS);
     const bool live = i < 3 * n;
     const int64_t ii = live ? i : 0;
-    const int64_t stride = 3 * n;
-    double a = 0.0;
-    if (live) {
-        for (int c0 = sub; c0 < chunks; c0 += GS * kLoadBatch) {
-            double v[kLoadBatch];
-#pragma unroll
-            for (int u = 0; u < kLoadBatch; ++u) {
-                const int c = c0 + u * GS;
-                v[u] = (c < chunks) ? part[(int64_t)c * stride + ii] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < kLoadBatch; ++u)
-                if (c0 + u * GS < chunks) a += v[u];
+    const bool head = live && sub == 0;
+    double p0 = 0.0, v0 = 0.0, vs0 = 0.0, sr0 = 0.0, sv0 = 0.0;
+    if (head) {
+        p0 = pos[i];
+        v0 = vel[i];
+        if (stage > 1) {
+            vs0 = vs[i];
+            sr0 = sr[i];
+            sv0 = sv[i];
         }
     }
-    if (GS > 1) {
-        double total = a;
-        const int lane = threadIdx.x & 63;
-#pragma unroll
-        for (int g = 1; g < GS; ++g) {
-            const double o = __shfl(a, lane + g, 64);
-            if (sub == 0) total += o;
-        }
-        a = total;
-    }
-    if (!live || sub != 0) return;
+    const double a = chunk_sum<GS>(part, chunks, 3 * n, ii, sub, live);
+    if (!head) return;
     bool finite = __builtin_isfinite(a);
-    const double kr = (stage == 1) ? vel[i] : vs[i];
+    const double kr = (stage == 1) ? v0 : vs0;
     if (stage < 4) {
         if (stage == 1) {
             sr[i] = kr;
             sv[i] = a;
         } else {
-            sr[i] = sr[i] + 2.0 * kr;
-            sv[i] = sv[i] + 2.0 * a;
+            sr[i] = sr0 + 2.0 * kr;
+            sv[i] = sv0 + 2.0 * a;
         }
         const double h = (stage == 3) ? dt : 0.5 * dt;
-        const double r = pos[i] + h * kr;
-        const double v = vel[i] + h * a;
+        const double r = p0 + h * kr;
+        const double v = v0 + h * a;
         finite = finite && __builtin_isfinite(r) && __builtin_isfinite(v);
         rs[i] = r;
         vs[i] = v;
     } else {
         const double h6 = dt / 6.0;
-        const double r = pos[i] + h6 * (sr[i] + kr);
-        const double v = vel[i] + h6 * (sv[i] + a);
+        const double r = p0 + h6 * (sr0 + kr);
+        const double v = v0 + h6 * (sv0 + a);
         finite = finite && __builtin_isfinite(r) && __builtin_isfinite(v);
         pos[i] = r;
         vel[i] = v;
@@ -401,14 +367,18 @@ hipError_t launch_step(const double* part, int chunks, const int8_t* body_chunks
     // below that, from 96 partials (the each-pair-once pass on large systems)
     // and for an ensemble's per-body counts, where each load of a wavefront
     // then reads 512 contiguous bytes of one partial plane (measured faster)
-    if (!body_chunks && chunks >= 16 && chunks < 96)
-        hipLaunchKernelGGL(k_step<4>, dim3(blocks_for(12 * n, kBlock)), dim3(kBlock), 0, s, part,
-                           chunks, body_chunks, n, vel, pos_in, pos_out, acc, 0.5 * dt, dt, mode,
-                           flags);
+    if (body_chunks)
+        hipLaunchKernelGGL((k_step<1, true>), dim3(blocks_for(3 * n, kBlock)), dim3(kBlock), 0, s,
+                           part, chunks, body_chunks, n, vel, pos_in, pos_out, acc, 0.5 * dt, dt,
+                           mode, flags);
+    else if (chunks >= 16 && chunks < 96)
+        hipLaunchKernelGGL((k_step<4, false>), dim3(blocks_for(12 * n, kBlock)), dim3(kBlock), 0,
+                           s, part, chunks, body_chunks, n, vel, pos_in, pos_out, acc, 0.5 * dt,
+                           dt, mode, flags);
     else
-        hipLaunchKernelGGL(k_step<1>, dim3(blocks_for(3 * n, kBlock)), dim3(kBlock), 0, s, part,
-                           chunks, body_chunks, n, vel, pos_in, pos_out, acc, 0.5 * dt, dt, mode,
-                           flags);
+        hipLaunchKernelGGL((k_step<1, false>), dim3(blocks_for(3 * n, kBlock)), dim3(kBlock), 0,
+                           s, part, chunks, body_chunks, n, vel, pos_in, pos_out, acc, 0.5 * dt,
+                           dt, mode, flags);
     return hipGetLastError();
 }
 
