@@ -28,11 +28,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+
 def metric_at(n):
     """The headline metric's name for a single system of n bodies."""
     return f"pair interactions/s + steps/s at N={n:,}: FP64 vs split-precision at fixed ΔE/E"
+
+
 FP64_PEAK_TFLOPS = 78.6          # MI355X vector FP64, 256 CU x 64 lanes x 2 x 2.4 GHz
 FP32_PEAK_TFLOPS = 157.3         # MI355X vector FP32 (packed)
+VJP_FLOPS_PER_PAIR = 47         # transpose-Jacobian pass of the adjoint, per ordered pair
 HBM_PEAK_GBS = 8000.0
 # algorithmic work of one force pass: 20 flops per ordered pair interaction,
 # N (N - 1) of them, whichever kernel evaluates them
@@ -251,37 +255,19 @@ def bench_single(args, k, S, nb, torch, np_, dev):
     v64, sps64 = rate(r64)
     vsp, spssp = rate(rsp)
 
-    # per-step acceleration error against the CPU oracle at the initial state
-    import oracle
-    if n <= 20000:
-        a_ref = oracle.accel(s.pos, s.mass, G)
-        idx = None
-    else:
-        rng = np.random.default_rng(0)
-        idx = np.unique(np.concatenate([[0, n - 1], rng.choice(n, 254, replace=False)]))
-        a_ref = oracle.accel_targets(s.pos, s.mass, G, idx)
-
-    def acc_err(prec):
-        a = nb.accel(pos0, m, G, precision=prec).cpu().numpy()
-        if idx is not None:
-            a = a[:, idx]
-        return float(np.max(np.linalg.norm(a - a_ref, axis=0) / np.linalg.norm(a_ref, axis=0)))
-
-    err64, errsp = acc_err("fp64"), acc_err("split")
     rcp = results["compensated"]
     vcp, spscp = rate(rcp)
-    mscp = nb.time_force(pos0, m, G, "compensated", reps=max(3, (args.force_reps or 20) // 2))
+    reps = args.force_reps or max(20, min(2000, int(2e11 / pairs)))
+    mscp = nb.time_force(pos0, m, G, "compensated", reps=reps)
     comp = {"pairs_per_s": vcp, "steps_per_s": spscp, "ms_per_step": 1e3 * rcp["wall"] / K,
             "dE_over_E": (rcp["E"] - E0) / abs(E0),
             "E_minus_E_fp64_over_E0": (rcp["E"] - r64["E"]) / abs(E0),
-            "accel_max_rel_err_vs_oracle": acc_err("compensated"),
             "speedup_vs_fp64": vcp / v64, "ms_per_launch": round(mscp, 5),
             "tile": nb.get_tile(0, "compensated", n), "gpu_event_s": rcp["gpu"],
             "form": "split as specified: FP64 d and r^2, FP32 rsqrt + one FP64 Newton step, "
                     "light terms in FP32 Kahan sums"}
 
     # force-kernel timing for the roofline (HIP events around the force kernels only)
-    reps = args.force_reps or max(20, min(2000, int(2e11 / pairs)))
     ms64 = nb.time_force(pos0, m, G, "fp64", reps=reps)
     mssp = nb.time_force(pos0, m, G, "split", reps=reps)
     t64 = tiles["fp64"]
@@ -309,11 +295,11 @@ def bench_single(args, k, S, nb, torch, np_, dev):
                    "n": n, "dt_days": dt, "steps": K, "tile": tiles["fp64"]},
         "steps_per_s": sps64,
         "fp64": {"pairs_per_s": v64, "steps_per_s": sps64, "dE_over_E": (r64["E"] - E0) / abs(E0),
-                 "accel_max_rel_err_vs_oracle": err64, "gpu_event_s": r64["gpu"]},
+                 "gpu_event_s": r64["gpu"]},
         "split": {"pairs_per_s": vsp, "steps_per_s": spssp, "ms_per_step": 1e3 * rsp["wall"] / K,
                   "dE_over_E": (rsp["E"] - E0) / abs(E0),
                   "E_split_minus_E_fp64_over_E0": (rsp["E"] - r64["E"]) / abs(E0),
-                  "accel_max_rel_err_vs_oracle": errsp, "speedup_vs_fp64": vsp / v64,
+                  "speedup_vs_fp64": vsp / v64,
                   "tile": tiles["split"], "gpu_event_s": rsp["gpu"]},
         "split_compensated": comp,
         "roofline": roof,
@@ -323,6 +309,7 @@ def bench_single(args, k, S, nb, torch, np_, dev):
         line["rk4"] = rk4_rate(nb, torch, pos0, vel0, m, G, dt, n)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds, k)
+        line["cpu_baseline"]["accel_max_rel_err_of_gpu"] = oracle_accel_errors(nb, s, pos0, m, G)
     print(json.dumps(line), flush=True)
 
 
@@ -374,6 +361,16 @@ def bench_force(args, S, nb, torch, np_, dev):
         log(f"force {prec}: {out[prec]['ms_per_launch']:.4f} ms per launch")
     out["roofline"] = roofline(n, out["fp64"]["tile"], out["fp64"]["ms_per_launch"],
                                out["split"]["ms_per_launch"])
+    # the adjoint's transpose-Jacobian pass at the same size: 47 flops per
+    # ordered pair (d 3, |d|^2 5, rsqrt 1, the powers 3, m_q u_j - m_j u_q 9,
+    # d.w 5, its scale 2, the tidal product 12, the mass term 7)
+    settle_clock(nb, pos0, m, G, "fp64", args.settle_ms)
+    msv = nb.time_force(pos0, m, G, "fp64", kind=1, reps=max(20, reps // 4))
+    tfv = VJP_FLOPS_PER_PAIR * n * (n - 1) / (msv * 1e-3) / 1e12
+    out["vjp"] = {"ms_per_launch": msv, "tile": nb.get_tile(1, "fp64", n),
+                  "flops_per_ordered_pair": VJP_FLOPS_PER_PAIR, "achieved_tflops": tfv,
+                  "frac": tfv / FP64_PEAK_TFLOPS}
+    log(f"vjp: {msv:.4f} ms per launch, {tfv:.2f} TFLOP/s ({tfv / FP64_PEAK_TFLOPS:.3f} of peak)")
     print(json.dumps(out), flush=True)
 
 
@@ -436,6 +433,30 @@ def cpu_baseline(s, budget_s, k):
             "sample": f"first {steps} steps of the same {n}-body run ({steps + 1} force passes, "
                       f"{t:.1f} s)",
             "host_cpus": os.cpu_count()}
+
+
+def oracle_accel_errors(nb, s, pos0, m, G):
+    """Part of the CPU-baseline leg: the largest relative error of each
+    precision form's accelerations at the initial state against the oracle
+    (all bodies up to 20,000, else the first, the last and 254 seeded ones)."""
+    import oracle
+    n = s.n
+    if n <= 20000:
+        a_ref = oracle.accel(s.pos, s.mass, G)
+        idx = None
+    else:
+        rng = np.random.default_rng(0)
+        idx = np.unique(np.concatenate([[0, n - 1], rng.choice(n, 254, replace=False)]))
+        a_ref = oracle.accel_targets(s.pos, s.mass, G, idx)
+    out = {}
+    for prec in ("fp64", "split", "compensated"):
+        a = nb.accel(pos0, m, G, precision=prec).cpu().numpy()
+        if idx is not None:
+            a = a[:, idx]
+        out[prec] = float(np.max(np.linalg.norm(a - a_ref, axis=0)
+                                 / np.linalg.norm(a_ref, axis=0)))
+    out["targets"] = "all" if idx is None else f"{len(idx)} sampled"
+    return out
 
 
 def bench_copy(torch, dev):
@@ -738,10 +759,30 @@ def bench_dt_scan(args, S, nb, torch, np_, dev):
 SCAN_N = (100, 131, 300, 1000, 3000, 10425, 30000, 131072)
 
 
-def bench_n_scan(args, S, nb, torch, np_, dev):
+def oracle_scan_rates(s, n):
+    """CPU-baseline leg of the N scan: the oracle's force-pass rate on one
+    thread and on all of them, over a sample of targets."""
     import oracle
-    rows = []
+    row = {}
     all_threads = oracle.get_threads()
+    for threads, budget in ((1, 1.5e8), (all_threads, 2.5e9)):
+        oracle.set_threads(threads)
+        count = int(min(n, max(1, budget / n)))
+        idx = np.linspace(0, n - 1, count).astype(np.int64)
+        reps, t0 = 0, time.perf_counter()
+        while reps == 0 or time.perf_counter() - t0 < 0.3:
+            oracle.accel_targets(s.pos, s.mass, s.G, idx)
+            reps += 1
+        dt_cpu = (time.perf_counter() - t0) / reps
+        row[f"oracle_{'all' if threads == all_threads else 1}t_pairs_per_s"] = \
+            count * (n - 1) / dt_cpu
+    oracle.set_threads(all_threads)
+    row["oracle_threads"] = all_threads
+    return row
+
+
+def bench_n_scan(args, S, nb, torch, np_, dev):
+    rows = []
     for i, n in enumerate(SCAN_N):
         s = S.solar_system(30 + i, n - 31, n_major=30, name=f"scan-{n}")
         pairs = n * (n - 1)
@@ -763,23 +804,13 @@ def bench_n_scan(args, S, nb, torch, np_, dev):
             wall = time.perf_counter() - t0
             row[prec] = {"pairs_per_s": (K + 1) * pairs / wall, "steps_per_s": K / wall,
                          "tile": nb.get_tile(0, prec, n)}
-        # the oracle on one thread and on all of them, over a sample of targets
-        for threads, budget in ((1, 1.5e8), (all_threads, 2.5e9)):
-            oracle.set_threads(threads)
-            count = int(min(n, max(1, budget / n)))
-            idx = np.linspace(0, n - 1, count).astype(np.int64)
-            reps, t0 = 0, time.perf_counter()
-            while reps == 0 or time.perf_counter() - t0 < 0.3:
-                oracle.accel_targets(s.pos, s.mass, s.G, idx)
-                reps += 1
-            dt_cpu = (time.perf_counter() - t0) / reps
-            row[f"oracle_{threads}t_pairs_per_s"] = count * (n - 1) / dt_cpu
-        oracle.set_threads(all_threads)
-        row["oracle_threads"] = all_threads
-        log(f"n={n}: fp64 {row['fp64']['pairs_per_s']:.3e} pairs/s "
-            f"({row['fp64']['steps_per_s']:.0f} steps/s), split {row['split']['pairs_per_s']:.3e}; "
-            f"oracle 1t {row['oracle_1t_pairs_per_s']:.3e}, "
-            f"{all_threads}t {row[f'oracle_{all_threads}t_pairs_per_s']:.3e}")
+        msg = (f"n={n}: fp64 {row['fp64']['pairs_per_s']:.3e} pairs/s "
+               f"({row['fp64']['steps_per_s']:.0f} steps/s), split {row['split']['pairs_per_s']:.3e}")
+        if not args.no_cpu_baseline:
+            row.update(oracle_scan_rates(s, n))
+            msg += (f"; oracle 1t {row['oracle_1t_pairs_per_s']:.3e}, "
+                    f"{row['oracle_threads']}t {row['oracle_allt_pairs_per_s']:.3e}")
+        log(msg)
         rows.append(row)
     print(json.dumps({"metric": "pair interactions/s against N", "unit": "pair interactions/s",
                       "n_gpus": 1, "dtype": "f64", "data": "synthetic",
