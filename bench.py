@@ -14,6 +14,7 @@ CPU oracle's rate on this host.
     python bench.py --workload dt-scan    # accuracy against the step size (Sec. 4)
     python bench.py --workload n-scan     # throughput against N, GPU and oracle (Sec. 5)
     python bench.py --workload force      # force passes only (for counter profiles)
+    python bench.py --workload shard      # one GPU's share of the targets (8-way split)
 """
 from __future__ import annotations
 
@@ -58,7 +59,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="solar-10425",
                     choices=["solar-10425", "solar-131", "solar-131072", "ensemble", "adjoint",
-                             "dt-scan", "n-scan", "copy", "force"])
+                             "dt-scan", "n-scan", "copy", "force", "shard"])
     ap.add_argument("--tune", action="store_true",
                     help="single-system workloads: autotune the force tiles first (the default "
                          "is the library's sweep-derived heuristic; the ensemble always autotunes)")
@@ -184,6 +185,8 @@ def main():
         return bench_n_scan(args, S, nb, torch, np, dev)
     if args.workload == "force":
         return bench_force(args, S, nb, torch, np, dev)
+    if args.workload == "shard":
+        return bench_shard(args, S, nb, torch, np, dev)
     k = {"solar-131": 0, "solar-10425": 1, "solar-131072": 2}[args.workload]
     return bench_single(args, k, S, nb, torch, np, dev)
 
@@ -372,6 +375,51 @@ def bench_force(args, S, nb, torch, np_, dev):
                   "frac": tfv / FP64_PEAK_TFLOPS}
     log(f"vjp: {msv:.4f} ms per launch, {tfv:.2f} TFLOP/s ({tfv / FP64_PEAK_TFLOPS:.3f} of peak)")
     print(json.dumps(out), flush=True)
+
+
+def bench_shard(args, S, nb, torch, np_, dev):
+    """One GPU's share of the force pass when the 131,072-body system's
+    targets are split over 8 GPUs (16,384 targets against all 131,072
+    sources each): every share timed on this GPU with HIP events around
+    back-to-back calls of nbody_accel_shard (work-list upload, G m, the
+    one-way force kernel and the fixed-order sum), beside the single-GPU
+    each-pair-once pass over the whole system."""
+    s = S.config(2)
+    n, G, gpus = s.n, s.G, 8
+    pos, m = _t(s.pos, torch, dev), _t(s.mass, torch, dev)
+    reps = args.force_reps or 20
+    w = -(-n // gpus)
+    rows = []
+    outs = [nb.accel_shard(pos, m, G, k * w, min(w, n - k * w)) for k in range(gpus)]  # work lists
+    settle_clock(nb, pos, m, G, "fp64", args.settle_ms)
+    for k in range(gpus):
+        t0, nt = k * w, min(w, n - k * w)
+        out = outs[k]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            nb.accel_shard(pos, m, G, t0, nt, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        pairs = nt * (n - 1)
+        tf = FLOPS_PER_PAIR * pairs / (ms * 1e-3) / 1e12
+        rows.append({"t0": t0, "nt": nt, "ms": ms, "pairs_per_s": pairs / (ms * 1e-3),
+                     "achieved_tflops": tf, "frac": tf / FP64_PEAK_TFLOPS})
+        log(f"share {k}: targets [{t0}, {t0 + nt}) {ms:.4f} ms, {pairs / (ms * 1e-3):.3e} pairs/s, "
+            f"frac {tf / FP64_PEAK_TFLOPS:.3f}")
+    ms_full = nb.time_force(pos, m, G, "fp64", reps=reps)
+    worst = max(r["ms"] for r in rows)
+    print(json.dumps({"metric": "one GPU's share of the force pass, 8-way split of the targets",
+                      "unit": "pair interactions/s", "n": n, "gpus_modelled": gpus, "reps": reps,
+                      "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": "solar-131072, seed 2; shares of 16,384 targets"},
+                      "tile": "one-way force kernel (the full pass's one-way tile, chunks per share)",
+                      "shares": rows, "slowest_share_ms": worst,
+                      "whole_pass_one_gpu_ms": ms_full,
+                      "whole_pass_one_gpu_tile": nb.get_tile(0, "fp64", n),
+                      "force_pass_speedup_8_shares_vs_one_gpu": ms_full / worst}), flush=True)
 
 
 def rk4_rate(nb, torch, pos0, vel0, m, G, dt, n, steps=1000):

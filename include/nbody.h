@@ -92,7 +92,9 @@ typedef enum {
     NBODY_OP_RK4 = 5,
     /* nbody_verlet_checkpoints and nbody_verlet_adjoint_from_checkpoints
      * (the adjoint's workspace without its checkpoints) */
-    NBODY_OP_ADJOINT_SWEEP = 6
+    NBODY_OP_ADJOINT_SWEEP = 6,
+    /* nbody_accel_shard (n_total = the system's n; precision NBODY_FP64) */
+    NBODY_OP_ACCEL_SHARD = 7
 } nbody_op;
 
 /* Bytes of workspace that `op` needs.  n_total: bodies (for BATCHED, the sum
@@ -110,6 +112,21 @@ int32_t nbody_accel(const double* pos, const double* vel, const double* mass,
                     int64_t n, double G, double dt, int64_t steps,
                     double* acc_out, int32_t precision, double small_mass,
                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* Eq. (1) for a contiguous share of the targets: acc_out[3 * nt] (planes of
+ * stride nt) = the FP64 accelerations of bodies t0 .. t0 + nt - 1 of the
+ * n-body system at pos, each summed over all n sources.  This is one GPU's
+ * force pass when the targets of a system are split among several GPUs that
+ * each hold every source position (the Sec. 3 decomposition: each process
+ * owns part of the bodies and needs all positions every step).  The pass is
+ * the one-way kernel (sources split into chunks, partials summed in a fixed
+ * chunk order), so the result is deterministic; it agrees with nbody_accel
+ * to rounding, not bit for bit.  0 <= t0, 1 <= nt, t0 + nt <= n.  Workspace:
+ * op NBODY_OP_ACCEL_SHARD for n.  Errors as nbody_accel; nothing is enqueued
+ * on an invalid argument. */
+int32_t nbody_accel_shard(const double* pos, const double* mass, int64_t n, double G,
+                          int64_t t0, int64_t nt, double* acc_out,
+                          void* workspace, size_t workspace_bytes, void* stream);
 
 /* Eqs. (3)-(4): advance (pos, vel) in place by `steps` velocity-Verlet steps
  * of size dt.  a(r_0) is computed first, then one evaluation of Eq. (1) per

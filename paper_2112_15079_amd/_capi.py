@@ -18,10 +18,12 @@ LIB_PATH = os.path.join(_HERE, "libnbody.so")
 
 NBODY_OK, NBODY_EINVAL, NBODY_EUNSUPPORTED, NBODY_EWORKSPACE, NBODY_EHIP = range(5)
 NBODY_FP64, NBODY_SPLIT, NBODY_SPLIT_COMPENSATED = 0, 1, 2
-OP_ACCEL, OP_RUN, OP_ADJOINT, OP_BATCHED, OP_ENERGY, OP_RK4, OP_ADJOINT_SWEEP = range(7)
+(OP_ACCEL, OP_RUN, OP_ADJOINT, OP_BATCHED, OP_ENERGY, OP_RK4, OP_ADJOINT_SWEEP,
+ OP_ACCEL_SHARD) = range(8)
 
 EXPORTS = (
-    "nbody_workspace_bytes", "nbody_accel", "nbody_verlet_run", "nbody_verlet_run_static",
+    "nbody_workspace_bytes", "nbody_accel", "nbody_accel_shard", "nbody_verlet_run",
+    "nbody_verlet_run_static",
     "nbody_rk4_run",
     "nbody_verlet_adjoint", "nbody_verlet_checkpoints", "nbody_verlet_adjoint_from_checkpoints",
     "nbody_verlet_run_batched", "nbody_energy", "nbody_momenta", "nbody_get_flags",
@@ -69,6 +71,8 @@ def load():
         lib.nbody_workspace_bytes.argtypes = [_I32, _I64, _I32, _I64, _I64, _I32]
         lib.nbody_accel.restype = _I32
         lib.nbody_accel.argtypes = [_P, _P, _P, _I64, _D, _D, _I64, _P, _I32, _D, _P, _SZ, _P]
+        lib.nbody_accel_shard.restype = _I32
+        lib.nbody_accel_shard.argtypes = [_P, _P, _I64, _D, _I64, _I64, _P, _P, _SZ, _P]
         lib.nbody_verlet_run.restype = _I32
         lib.nbody_verlet_run.argtypes = [_P, _P, _P, _I64, _D, _D, _I64, _I32, _D, _P, _SZ, _P]
         lib.nbody_verlet_run_static.restype = _I32

@@ -203,9 +203,10 @@ Layout layout(int op, int64_t n, int32_t ns, int64_t steps, int64_t K, int prec)
     Alloc a;
     const size_t d = sizeof(double);
     L.flags = a.take(256);
-    const int cap = op == NBODY_OP_BATCHED ? kBatchSlots
-                  : op == NBODY_OP_ENERGY  ? chunk_cap(n)
-                                           : part_slots(n);
+    const int cap = op == NBODY_OP_BATCHED     ? kBatchSlots
+                  : op == NBODY_OP_ENERGY      ? chunk_cap(n)
+                  : op == NBODY_OP_ACCEL_SHARD ? kMaxChunks
+                                               : part_slots(n);
     const bool adj = op == NBODY_OP_ADJOINT || op == NBODY_OP_ADJOINT_SWEEP;
     const int planes = adj ? 4 : 3;
     L.part = a.take((size_t)cap * planes * n * d);
@@ -226,6 +227,8 @@ Layout layout(int op, int64_t n, int32_t ns, int64_t steps, int64_t K, int prec)
         L.rk_sr = a.take(3 * n * d);
         L.rk_sv = a.take(3 * n * d);
     }
+    if (op == NBODY_OP_ACCEL_SHARD)   // target blocks of >= 64 bodies times <= kMaxChunks chunks
+        L.units = a.take((size_t)(n / 64 + 2) * kMaxChunks * sizeof(BatchUnit));
     if (op == NBODY_OP_BATCHED) {
         if (!L.offs) L.offs = a.take((size_t)(ns + 1) * sizeof(int64_t));
         // units: per system ceil(n_k/64) target blocks (the smallest tile) times
@@ -619,7 +622,8 @@ size_t nbody_workspace_bytes(int32_t op, int64_t n_total, int32_t num_systems, i
                              int64_t checkpoint_every, int32_t precision)
 {
     if (n_total < 1 || n_total > kMaxBodies || num_systems < 1) return 0;
-    if (op < NBODY_OP_ACCEL || op > NBODY_OP_ADJOINT_SWEEP) return 0;
+    if (op < NBODY_OP_ACCEL || op > NBODY_OP_ACCEL_SHARD) return 0;
+    if (op == NBODY_OP_ACCEL_SHARD && (precision != NBODY_FP64 || num_systems != 1)) return 0;
     if (precision != NBODY_FP64 && precision != NBODY_SPLIT &&
         precision != NBODY_SPLIT_COMPENSATED)
         return 0;
@@ -1267,6 +1271,20 @@ void drop_batch_plans()
 
 constexpr int64_t kBatchChunkLen = 1024;   // sources per chunk in the ensemble
 
+// Drops the least recently used work list when the cache is full.  Call with
+// g_mu held.
+void evict_batch_plan_locked()
+{
+    if (g_batch.size() < kMaxBatchPlans) return;
+    // uploads of the dropped plan read its host vectors asynchronously
+    (void)hipDeviceSynchronize();
+    auto victim = g_batch.begin();
+    for (auto jt = g_batch.begin(); jt != g_batch.end(); ++jt)
+        if (g_batch_used[jt->first] < g_batch_used[victim->first]) victim = jt;
+    g_batch_used.erase(victim->first);
+    g_batch.erase(victim);
+}
+
 std::shared_ptr<BatchPlan> batch_plan(const int64_t* offs, int32_t ns, const Tile& t)
 {
     std::vector<int64_t> key(offs, offs + ns + 1);
@@ -1277,15 +1295,7 @@ std::shared_ptr<BatchPlan> batch_plan(const int64_t* offs, int32_t ns, const Til
     g_batch_used[key] = ++g_batch_tick;
     auto it = g_batch.find(key);
     if (it != g_batch.end()) return it->second;
-    if (g_batch.size() >= kMaxBatchPlans) {
-        // uploads of the dropped plan read its host vectors asynchronously
-        (void)hipDeviceSynchronize();
-        auto victim = g_batch.begin();
-        for (auto jt = g_batch.begin(); jt != g_batch.end(); ++jt)
-            if (g_batch_used[jt->first] < g_batch_used[victim->first]) victim = jt;
-        g_batch_used.erase(victim->first);
-        g_batch.erase(victim);
-    }
+    evict_batch_plan_locked();
     auto bp = std::make_shared<BatchPlan>();
     bp->offsets.assign(offs, offs + ns + 1);
     const int64_t n_total = offs[ns];
@@ -1462,9 +1472,88 @@ int batched_split_prepare(const double* pos, const double* vel, const double* ma
     return NBODY_OK;
 }
 
+// ---------------------------------------------------------------------------
+// a share of the targets (one GPU's force pass when the targets are split)
+
+// The one-way tile of the full pass over n bodies, with its source chunks
+// chosen for the share's target blocks: about 8192 / waves units, as the
+// full pass has, capped by the chunk limit and at 64 * waves sources each.
+Tile shard_tile(int64_t n, int64_t t0, int64_t nt)
+{
+    Tile t = force_only_tile(NBODY_FP64, n);
+    const int64_t tpb = targets_per_block(t);
+    const int64_t tb = (t0 + nt - 1) / tpb - t0 / tpb + 1;
+    int64_t c = std::max<int64_t>(1, 8192 / (tb * t.waves));
+    c = std::min<int64_t>(c, std::max<int64_t>(1, n / (64 * t.waves)));
+    t.chunks = (int)std::min<int64_t>(c, kMaxChunks);
+    return t;
+}
+
+// Work list of a share: the target blocks holding t0 .. t0 + nt - 1 times the
+// tile's chunks (a single system at body 0), cached with the ensembles' lists.
+std::shared_ptr<BatchPlan> shard_plan(int64_t n, int64_t t0, int64_t nt, const Tile& t)
+{
+    std::vector<int64_t> key = {-1, n, t0, nt, t.tpl, t.waves, t.chunks, t.variant};
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_batch_used[key] = ++g_batch_tick;
+    auto it = g_batch.find(key);
+    if (it != g_batch.end()) return it->second;
+    evict_batch_plan_locked();
+    auto bp = std::make_shared<BatchPlan>();
+    const int64_t tpb = targets_per_block(t);
+    const int eff = effective_chunks(n, t);
+    for (int64_t b = t0 / tpb; b <= (t0 + nt - 1) / tpb; ++b)
+        for (int c = 0; c < eff; ++c) {
+            BatchUnit u;
+            u.body0 = 0;
+            u.n = (int32_t)n;
+            u.sys = 0;
+            u.tblock = (int32_t)b;
+            u.chunk = c;
+            u.chunks = t.chunks;
+            u.pad = 0;
+            bp->units.push_back(u);
+        }
+    g_batch[key] = bp;
+    return bp;
+}
+
 }  // namespace
 
 extern "C" {
+
+int32_t nbody_accel_shard(const double* pos, const double* mass, int64_t n, double G, int64_t t0,
+                          int64_t nt, double* acc_out, void* workspace, size_t workspace_bytes,
+                          void* stream)
+{
+    g_err.clear();
+    NB_TRY(check_common(pos, mass, n, G));
+    if (!acc_out) return fail(NBODY_EINVAL, "acc_out is NULL");
+    if (t0 < 0 || nt < 1 || t0 > n - nt)
+        return fail(NBODY_EINVAL, "targets [%lld, %lld) are not a non-empty part of [0, %lld)",
+                    (long long)t0, (long long)(t0 + nt), (long long)n);
+    const Layout L = layout(NBODY_OP_ACCEL_SHARD, n, 1, 0, 1, NBODY_FP64);
+    NB_TRY(check_ws(workspace, workspace_bytes, L.total));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Tile t = shard_tile(n, t0, nt);
+    auto bp = shard_plan(n, t0, nt, t);
+    const int64_t nu = (int64_t)bp->units.size();
+    if ((size_t)nu * sizeof(BatchUnit) > L.total - L.units)   // (the layout's bound covers it)
+        return fail(NBODY_EUNSUPPORTED, "work list exceeds the workspace");
+    BatchUnit* units = at<BatchUnit>(workspace, L.units);
+    double* part = at<double>(workspace, L.part);
+    double* gm = at<double>(workspace, L.gm);
+    NB_HIP(hipMemcpyAsync(units, bp->units.data(), nu * sizeof(BatchUnit), hipMemcpyHostToDevice,
+                          s));
+    NB_HIP(launch_scale(mass, G, n, gm, s));
+    int cus = 0;
+    NB_TRY(device_cus(&cus));
+    const int grid = (int)std::min<int64_t>(nu, (int64_t)cus * (16 / t.waves));
+    NB_HIP(launch_force_batched(NBODY_FP64, t, pos, mass, gm, n, G, units, nu, nullptr, grid, part,
+                                s));
+    NB_HIP(launch_shard_sum(part, effective_chunks(n, t), n, t0, nt, acc_out, s));
+    return NBODY_OK;
+}
 
 int32_t nbody_verlet_run_batched(double* pos, double* vel, const double* mass,
                                  const int64_t* offsets_host, int32_t num_systems, double G,

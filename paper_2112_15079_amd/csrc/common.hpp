@@ -131,6 +131,10 @@ hipError_t launch_step_fused(int precision, const Tile& tile, const double* pos_
 hipError_t launch_step(const double* part, int chunks, const int8_t* body_chunks, int64_t n,
                        double* vel, const double* pos_in, double* pos_out, double* acc,
                        double dt, int mode, uint32_t* flags, hipStream_t s);
+// out[k * nt + q] = sum_{c < chunks} part[c][k][t0 + q] in ascending c, for
+// the targets t0 .. t0 + nt - 1 of an n-body system (a share of the targets).
+hipError_t launch_shard_sum(const double* part, int chunks, int64_t n, int64_t t0, int64_t nt,
+                            double* out, hipStream_t s);
 
 // ----- fourth-order Runge-Kutta (the alternative integrator of Sec. 2) ---------
 // Stage s = 1..4 after the force pass at the stage position (pos for s = 1,

@@ -61,6 +61,25 @@ __global__ __launch_bounds__(kBlock) void k_step(const double* __restrict__ part
     if (!finite && flags) atomicOr(flags, 1u);
 }
 
+// The accelerations of targets t0 .. t0 + nt - 1 from the chunk partials of
+// a pass over those targets (GS threads per (component, target) element,
+// summed by chunk_sum), into planes of stride nt.
+template <int GS>
+__global__ __launch_bounds__(kBlock) void k_shard_sum(const double* __restrict__ part,
+                                                      int chunks, int64_t n, int64_t t0,
+                                                      int64_t nt, double* __restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t e = t / GS;   // k * nt + q
+    const int sub = (int)(t % GS);
+    const bool live = e < 3 * nt;
+    const int64_t ee = live ? e : 0;
+    const int64_t k = ee / nt;
+    const int64_t q = ee - k * nt;
+    const double a = chunk_sum<GS>(part, chunks, 3 * n, k * n + t0 + q, sub, live);
+    if (live && sub == 0) out[e] = a;
+}
+
 // Classical fourth-order Runge-Kutta (r' = v, v' = a(r)): stage s's
 // acceleration a (the chunk partials of the force pass at the stage position,
 // summed in ascending chunk order) and the stage velocity give the slopes
@@ -379,6 +398,18 @@ hipError_t launch_step(const double* part, int chunks, const int8_t* body_chunks
         hipLaunchKernelGGL((k_step<1, false>), dim3(blocks_for(3 * n, kBlock)), dim3(kBlock), 0,
                            s, part, chunks, body_chunks, n, vel, pos_in, pos_out, acc, 0.5 * dt,
                            dt, mode, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_shard_sum(const double* part, int chunks, int64_t n, int64_t t0, int64_t nt,
+                            double* out, hipStream_t s)
+{
+    if (chunks >= 16 && chunks < 96)
+        hipLaunchKernelGGL(k_shard_sum<4>, dim3(blocks_for(12 * nt, kBlock)), dim3(kBlock), 0, s,
+                           part, chunks, n, t0, nt, out);
+    else
+        hipLaunchKernelGGL(k_shard_sum<1>, dim3(blocks_for(3 * nt, kBlock)), dim3(kBlock), 0, s,
+                           part, chunks, n, t0, nt, out);
     return hipGetLastError();
 }
 

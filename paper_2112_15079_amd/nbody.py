@@ -87,6 +87,24 @@ def accel(pos, mass, G, precision="fp64", small_mass=None, out=None):
     return out
 
 
+def accel_shard(pos, mass, G, t0, nt, out=None):
+    """FP64 Eq. (1) accelerations of bodies t0 .. t0 + nt - 1 from all n
+    sources (one GPU's share of the targets); returns a (3, nt) tensor."""
+    n = _mass(mass)
+    _state(pos, "pos", n)
+    dev = _same_device(pos, mass)
+    t0, nt = int(t0), int(nt)
+    if out is None:
+        out = torch.empty((3, max(nt, 1)), dtype=torch.float64, device=dev)
+    _state(out, "out", max(nt, 1))
+    lib = C.load()
+    ws = C.workspace(C.workspace_bytes(C.OP_ACCEL_SHARD, n), dev)
+    st = lib.nbody_accel_shard(pos.data_ptr(), mass.data_ptr(), n, float(G), t0, nt,
+                               out.data_ptr(), ws.data_ptr(), ws.numel(), C.stream_handle(dev))
+    C.check(st, "nbody_accel_shard")
+    return out
+
+
 def verlet_run(pos, vel, mass, G, dt, steps, precision="fp64", small_mass=None):
     """Advances (pos, vel) in place by ``steps`` velocity-Verlet steps
     (Eqs. (3)-(4)); returns (pos, vel)."""

@@ -323,3 +323,27 @@ def test_split_adjoint_validates_first():
     sweep = wsb(C.OP_ADJOINT_SWEEP, 2079, 1, 36500, 100, 0)
     assert 0 < sweep < full and full - sweep >= 366 * 6 * 2079 * 8
     assert wsb(C.OP_ADJOINT_SWEEP, 10, 1, 5, 0, 0) == 0
+
+
+def test_target_share_validates_first():
+    """nbody_accel_shard: a share of the targets must be a non-empty part of
+    [0, n); bad arguments and short workspaces are refused before any device
+    work.  Its workspace is sized for FP64 and one system only."""
+    lib = _lib()
+    ws = ctypes.c_void_p(0x100000)
+    big = 1 << 40
+    sh = lib.nbody_accel_shard
+    assert sh(None, FAKE, 10, 1.0, 0, 5, FAKE, ws, big, None) == C.NBODY_EINVAL
+    assert sh(FAKE, FAKE, 10, 1.0, 0, 5, None, ws, big, None) == C.NBODY_EINVAL
+    assert sh(FAKE, FAKE, 0, 1.0, 0, 1, FAKE, ws, big, None) == C.NBODY_EINVAL
+    assert sh(FAKE, FAKE, 10, float("nan"), 0, 5, FAKE, ws, big, None) == C.NBODY_EINVAL
+    for t0, nt in ((-1, 5), (0, 0), (6, 5), (10, 1), (0, 11), (9, -3)):
+        assert sh(FAKE, FAKE, 10, 1.0, t0, nt, FAKE, ws, big, None) == C.NBODY_EINVAL, (t0, nt)
+        assert "targets" in C.last_error()
+    assert sh(FAKE, FAKE, 10, 1.0, 0, 10, FAKE, None, big, None) == C.NBODY_EWORKSPACE
+    assert sh(FAKE, FAKE, 10, 1.0, 0, 10, FAKE, ws, 64, None) == C.NBODY_EWORKSPACE
+    wsb = lib.nbody_workspace_bytes
+    # 64 chunk partials of every body, the G m plane and the work list
+    assert wsb(C.OP_ACCEL_SHARD, 131072, 1, 0, 1, 0) >= 64 * 3 * 131072 * 8 + 131072 * 8
+    assert wsb(C.OP_ACCEL_SHARD, 131072, 1, 0, 1, 1) == 0
+    assert wsb(C.OP_ACCEL_SHARD, 131072, 2, 0, 1, 0) == 0
