@@ -367,13 +367,19 @@ def bench_force(args, S, nb, torch, np_, dev):
     # the adjoint's transpose-Jacobian pass at the same size: 47 flops per
     # ordered pair (d 3, |d|^2 5, rsqrt 1, the powers 3, m_q u_j - m_j u_q 9,
     # d.w 5, its scale 2, the tidal product 12, the mass term 7)
+    # (the default tile: each pair once at this size; the one-way pass beside it)
     settle_clock(nb, pos0, m, G, "fp64", args.settle_ms)
-    msv = nb.time_force(pos0, m, G, "fp64", kind=1, reps=max(20, reps // 4))
-    tfv = VJP_FLOPS_PER_PAIR * n * (n - 1) / (msv * 1e-3) / 1e12
-    out["vjp"] = {"ms_per_launch": msv, "tile": nb.get_tile(1, "fp64", n),
-                  "flops_per_ordered_pair": VJP_FLOPS_PER_PAIR, "achieved_tflops": tfv,
-                  "frac": tfv / FP64_PEAK_TFLOPS}
-    log(f"vjp: {msv:.4f} ms per launch, {tfv:.2f} TFLOP/s ({tfv / FP64_PEAK_TFLOPS:.3f} of peak)")
+    for key, tile in (("vjp", None), ("vjp_one_way", (1, 2, 64, 1))):
+        if tile is not None:
+            nb.set_tile(1, "fp64", n, *tile)
+        msv = nb.time_force(pos0, m, G, "fp64", kind=1, reps=max(20, reps // 4))
+        tfv = VJP_FLOPS_PER_PAIR * n * (n - 1) / (msv * 1e-3) / 1e12
+        out[key] = {"ms_per_launch": msv, "tile": nb.get_tile(1, "fp64", n),
+                    "flops_per_ordered_pair": VJP_FLOPS_PER_PAIR, "achieved_tflops": tfv,
+                    "frac": tfv / FP64_PEAK_TFLOPS}
+        log(f"{key}: {msv:.4f} ms per launch, {tfv:.2f} TFLOP/s "
+            f"({tfv / FP64_PEAK_TFLOPS:.3f} of peak)")
+    nb.reset_caches()
     print(json.dumps(out), flush=True)
 
 

@@ -86,6 +86,15 @@ int mutual_ranges(int64_t n);
 // Partial slots of a single system's pass: the ranges, plus the extra slots
 // of the split last round (shape (4, 4) only).
 int mutual_slots(int64_t n, int tpl, int waves);
+// Largest single system the each-pair-once passes take (one partial slot per
+// range of 256 bodies: 512 at the largest).
+constexpr int64_t kMutualMaxN = 131072;
+// The adjoint's transpose-Jacobian pass with each unordered pair once: four
+// partial planes per slot (position gradient, mass gradient), one slot per
+// range (mutual_ranges(n)), in the layout launch_vjp_reduce sums.
+hipError_t launch_vjp_mutual(int tpl, int waves, const double* pos, const double* mass,
+                             const double* lam, double cu, int64_t n, double G, double* part,
+                             hipStream_t s);
 bool mutual_shape_supported(int tpl, int waves);
 hipError_t launch_force_mutual(int precision, int tpl, int waves, const double* pos,
                                const double* gm, int64_t n, const int64_t* nmaj, double* part,

@@ -339,6 +339,7 @@ int64_t vjp_chunk_length(int64_t n, const Tile& t)
 
 int vjp_chunks(int64_t n, const Tile& t)
 {
+    if (t.variant == 5) return mutual_ranges(n);   // each pair once: one slot per range
     const int64_t L = vjp_chunk_length(n, t);
     return (int)((n + L - 1) / L);
 }
@@ -346,6 +347,8 @@ int vjp_chunks(int64_t n, const Tile& t)
 hipError_t launch_vjp(const Tile& tile, const double* pos, const double* mass, const double* lam,
                       double cu, int64_t n, double G, double* part, hipStream_t s)
 {
+    if (tile.variant == 5)
+        return launch_vjp_mutual(tile.tpl, tile.waves, pos, mass, lam, cu, n, G, part, s);
     if (tile.variant != 0 && tile.variant != 1) return hipErrorInvalidValue;
     const int64_t L = vjp_chunk_length(n, tile);
     const int chunks = vjp_chunks(n, tile);

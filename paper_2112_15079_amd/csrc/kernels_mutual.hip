@@ -850,6 +850,262 @@ __global__ __launch_bounds__(64 * KMW) void k_force_mutual_batched(
                                 whole, -1, 0);
 }
 
+// ---------------------------------------------------------------------------
+// The transpose Jacobian of Eq. (1) (the adjoint's inner pass) with each
+// unordered pair evaluated once.  For a cotangent u on the accelerations and
+// the pair (q, j), d = r_j - r_q, K(d) = I/|d|^3 - 3 d d^T/|d|^5:
+//   body q gains  G K(d) w,      w = m_q u_j - m_j u_q,
+//   body j gains -G K(d) w       (K is even in d, w odd in the pair),
+// and in the mass gradient q gains -G u_j.d/|d|^3, j gains +G u_q.d/|d|^3.
+// The pass runs on lam (u = c lam) and scales by G c at the store, as the
+// one-way pass does.  Schedule as the force pass above, whole range pairs
+// only: the four reaction sums (three position components, the mass term)
+// travel along the row with their source.  Partial slot c of plane k (0..2:
+// position gradient, 3: mass gradient) of body i at part[(4c + k) n + i];
+// slot r holds workgroup (g, r)'s target sums, slot g its reactions, so a
+// body receives exactly one partial per range.
+
+struct VBody {
+    double x, y, z, m, ux, uy, uz;
+};
+
+// Padding bodies are massless, far away, at distinct points and carry no
+// cotangent, so every term they take part in is zero or is not stored.
+__device__ __forceinline__ VBody load_vbody(const double* __restrict__ pos,
+                                            const double* __restrict__ mass,
+                                            const double* __restrict__ lam, int64_t n, int64_t i)
+{
+    VBody b;
+    if (i < n) {
+        b.x = pos[i];
+        b.y = pos[n + i];
+        b.z = pos[2 * n + i];
+        b.m = mass[i];
+        b.ux = lam[i];
+        b.uy = lam[n + i];
+        b.uz = lam[2 * n + i];
+    } else {
+        b.x = kPadBase + kPadStep * (double)i;
+        b.y = kPadBase;
+        b.z = kPadBase;
+        b.m = 0.0;
+        b.ux = 0.0;
+        b.uy = 0.0;
+        b.uz = 0.0;
+    }
+    return b;
+}
+
+struct VSrc {   // the staged source blocks: seven planes, groups of 16 doubled
+    double x[kMM][128], y[kMM][128], z[kMM][128], m[kMM][128], ux[kMM][128], uy[kMM][128],
+        uz[kMM][128];
+};
+
+struct VAcc {
+    double x, y, z, g;
+};
+
+// One tile (KMT target blocks of a wave against source block jb), the
+// geometry of tile_sweep: targets t < NSYM both ways, t == NSYM one way when
+// DIAG (the diagonal block, its own body skipped), t > NSYM not at all.
+template <int KMT, int NSYM, bool DIAG>
+__device__ __forceinline__ void vjp_tile(const VSrc& S, int jb, double* __restrict__ ra, int lane,
+                                         const VBody (&tg)[KMT], VAcc (&o)[KMT])
+{
+    constexpr bool kReact = NSYM > 0;
+    const int row = lane >> 4;
+    const int col = lane & 15;
+    for (int q = 0; q < 4; ++q) {
+        const int grp = (row + q) & 3;
+        const int home = 16 * grp + col;
+        double rx = 0.0, ry = 0.0, rz = 0.0, rg = 0.0;
+#pragma unroll 2
+        for (int k = 0; k < 16; ++k) {
+            const int jj = 32 * grp + col + k;
+            const double jx = S.x[jb][jj], jy = S.y[jb][jj], jz = S.z[jb][jj], jm = S.m[jb][jj];
+            const double jux = S.ux[jb][jj], juy = S.uy[jb][jj], juz = S.uz[jb][jj];
+#pragma unroll
+            for (int t = 0; t < KMT; ++t) {
+                if (t > NSYM || (t == NSYM && !DIAG)) continue;
+                if (t == NSYM && q == 0 && k == 0) continue;   // the target itself
+                const double dx = jx - tg[t].x;
+                const double dy = jy - tg[t].y;
+                const double dz = jz - tg[t].z;
+                const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+                const double y = rinv_f64(r2);
+                const double y2 = y * y;
+                const double i3 = y * y2;
+                const double i5 = i3 * y2;
+                const double wx = __builtin_fma(-jm, tg[t].ux, tg[t].m * jux);
+                const double wy = __builtin_fma(-jm, tg[t].uy, tg[t].m * juy);
+                const double wz = __builtin_fma(-jm, tg[t].uz, tg[t].m * juz);
+                const double dw = __builtin_fma(dz, wz, __builtin_fma(dy, wy, dx * wx));
+                const double c = 3.0 * dw * i5;
+                o[t].x = __builtin_fma(-c, dx, __builtin_fma(wx, i3, o[t].x));
+                o[t].y = __builtin_fma(-c, dy, __builtin_fma(wy, i3, o[t].y));
+                o[t].z = __builtin_fma(-c, dz, __builtin_fma(wz, i3, o[t].z));
+                const double ujd = __builtin_fma(juz, dz, __builtin_fma(juy, dy, jux * dx));
+                o[t].g = __builtin_fma(ujd, i3, o[t].g);
+                if (t < NSYM) {   // the reaction on the source
+                    rx = __builtin_fma(c, dx, __builtin_fma(-wx, i3, rx));
+                    ry = __builtin_fma(c, dy, __builtin_fma(-wy, i3, ry));
+                    rz = __builtin_fma(c, dz, __builtin_fma(-wz, i3, rz));
+                    const double uqd =
+                        __builtin_fma(tg[t].uz, dz, __builtin_fma(tg[t].uy, dy, tg[t].ux * dx));
+                    rg = __builtin_fma(-uqd, i3, rg);
+                }
+            }
+            if (kReact) {
+                rx = row_next(rx);
+                ry = row_next(ry);
+                rz = row_next(rz);
+                rg = row_next(rg);
+            }
+        }
+        if (kReact) {
+            ra[home] += rx;
+            ra[64 + home] += ry;
+            ra[128 + home] += rz;
+            ra[192 + home] += rg;
+        }
+    }
+}
+
+template <int KMT>
+__device__ __forceinline__ void vjp_tile_dispatch(int d, const VSrc& S, int jb, double* ra,
+                                                  int lane, const VBody (&tg)[KMT],
+                                                  VAcc (&o)[KMT])
+{
+    // d = J - I0: targets I0 + t < J for t < d, I0 + d == J
+    if (d >= KMT) {
+        vjp_tile<KMT, KMT, false>(S, jb, ra, lane, tg, o);
+        return;
+    }
+    switch (d) {
+    case 0: vjp_tile<KMT, 0, true>(S, jb, ra, lane, tg, o); break;
+    case 1: vjp_tile<KMT, (KMT > 1 ? 1 : 0), true>(S, jb, ra, lane, tg, o); break;
+    case 2: vjp_tile<KMT, (KMT > 2 ? 2 : 0), true>(S, jb, ra, lane, tg, o); break;
+    case 3: vjp_tile<KMT, (KMT > 3 ? 3 : 0), true>(S, jb, ra, lane, tg, o); break;
+    default: break;
+    }
+}
+
+template <int KMT, int KMW>
+__global__ __launch_bounds__(64 * KMW) void k_vjp_mutual(const double* __restrict__ pos,
+                                                         const double* __restrict__ mass,
+                                                         const double* __restrict__ lam,
+                                                         double gc, int64_t n, int R,
+                                                         double* __restrict__ part)
+{
+    using Shape = MutualShape<KMT, KMW>;
+    __shared__ VSrc S;
+    __shared__ double racc[kMM][4][64];
+    __shared__ double comb[Shape::kShare > 1 ? Shape::kShare - 1 : 1][Shape::kSets][KMT][4][64];
+
+    const MutualTail whole{R, (int)((int64_t)R * (R + 1) / 2), 0, 0};
+    int g, r, half, xslot;
+    mt_decode(whole, blockIdx.x, g, r, half, xslot);
+
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int set = w % Shape::kSets;
+    const int h = w / Shape::kSets;
+    const int nb = (int)((n + 63) / 64);
+    const int I0 = g * kMM + set * KMT;
+    const int J0 = r * kMM;
+    const int64_t plane = 4 * n;
+
+    VBody tg[KMT];
+    VAcc o[KMT];
+#pragma unroll
+    for (int t = 0; t < KMT; ++t) {
+        tg[t] = load_vbody(pos, mass, lam, n, (int64_t)(I0 + t) * 64 + lane);
+        o[t] = VAcc{0.0, 0.0, 0.0, 0.0};
+    }
+    for (int jb = w; jb < kMM; jb += KMW) {
+        const VBody b = load_vbody(pos, mass, lam, n, (int64_t)(J0 + jb) * 64 + lane);
+        const int a0 = 32 * (lane >> 4) + (lane & 15);
+        S.x[jb][a0] = b.x; S.x[jb][a0 + 16] = b.x;
+        S.y[jb][a0] = b.y; S.y[jb][a0 + 16] = b.y;
+        S.z[jb][a0] = b.z; S.z[jb][a0 + 16] = b.z;
+        S.m[jb][a0] = b.m; S.m[jb][a0 + 16] = b.m;
+        S.ux[jb][a0] = b.ux; S.ux[jb][a0 + 16] = b.ux;
+        S.uy[jb][a0] = b.uy; S.uy[jb][a0 + 16] = b.uy;
+        S.uz[jb][a0] = b.uz; S.uz[jb][a0 + 16] = b.uz;
+        for (int k = 0; k < 4; ++k) racc[jb][k][lane] = 0.0;
+    }
+    __syncthreads();
+    for (int p = 0; p < Shape::kPhases; ++p) {
+        const int jb = (w + p) % kMM;
+        const int J = J0 + jb;
+        if (J < nb && J >= I0) vjp_tile_dispatch<KMT>(J - I0, S, jb, &racc[jb][0][0], lane, tg, o);
+        __syncthreads();
+    }
+
+    if (Shape::kShare > 1) {   // the sums of the waves sharing a target set, in wave order
+        if (h > 0) {
+#pragma unroll
+            for (int t = 0; t < KMT; ++t) {
+                comb[h - 1][set][t][0][lane] = o[t].x;
+                comb[h - 1][set][t][1][lane] = o[t].y;
+                comb[h - 1][set][t][2][lane] = o[t].z;
+                comb[h - 1][set][t][3][lane] = o[t].g;
+            }
+        }
+        __syncthreads();
+        if (h == 0) {
+            for (int k = 0; k < Shape::kShare - 1; ++k) {
+#pragma unroll
+                for (int t = 0; t < KMT; ++t) {
+                    o[t].x += comb[k][set][t][0][lane];
+                    o[t].y += comb[k][set][t][1][lane];
+                    o[t].z += comb[k][set][t][2][lane];
+                    o[t].g += comb[k][set][t][3][lane];
+                }
+            }
+        }
+    }
+
+    if (r > g) {   // targets' sums to slot r, the sources' reactions to slot g
+        if (h == 0) {
+#pragma unroll
+            for (int t = 0; t < KMT; ++t) {
+                const int64_t i = (int64_t)(I0 + t) * 64 + lane;
+                if (i < n) {
+                    double* pt = part + (int64_t)r * plane;
+                    __builtin_nontemporal_store(gc * o[t].x, &pt[i]);
+                    __builtin_nontemporal_store(gc * o[t].y, &pt[n + i]);
+                    __builtin_nontemporal_store(gc * o[t].z, &pt[2 * n + i]);
+                    __builtin_nontemporal_store(-gc * o[t].g, &pt[3 * n + i]);
+                }
+            }
+        }
+        for (int jb = w; jb < kMM; jb += KMW) {
+            const int64_t j = (int64_t)(J0 + jb) * 64 + lane;
+            if (j < n) {
+                double* ps = part + (int64_t)g * plane;
+                __builtin_nontemporal_store(gc * racc[jb][0][lane], &ps[j]);
+                __builtin_nontemporal_store(gc * racc[jb][1][lane], &ps[n + j]);
+                __builtin_nontemporal_store(gc * racc[jb][2][lane], &ps[2 * n + j]);
+                __builtin_nontemporal_store(-gc * racc[jb][3][lane], &ps[3 * n + j]);
+            }
+        }
+    } else if (h == 0) {   // the diagonal: each body's sum and the reaction on it
+#pragma unroll
+        for (int t = 0; t < KMT; ++t) {
+            const int64_t i = (int64_t)(I0 + t) * 64 + lane;
+            const int jb = set * KMT + t;
+            if (i < n) {
+                double* pt = part + (int64_t)g * plane;
+                __builtin_nontemporal_store(gc * (o[t].x + racc[jb][0][lane]), &pt[i]);
+                __builtin_nontemporal_store(gc * (o[t].y + racc[jb][1][lane]), &pt[n + i]);
+                __builtin_nontemporal_store(gc * (o[t].z + racc[jb][2][lane]), &pt[2 * n + i]);
+                __builtin_nontemporal_store(-gc * (o[t].g + racc[jb][3][lane]), &pt[3 * n + i]);
+            }
+        }
+    }
+}
+
 }  // namespace
 
 int mutual_ranges(int64_t n) { return (int)((((n + 63) / 64) + kMM - 1) / kMM); }
@@ -971,6 +1227,27 @@ hipError_t launch_force_mutual(int precision, int tpl, int waves, const double* 
         launch_mutual_shape<1>(tpl, waves, grid, pos, gm, n, nmaj, tl, part, s);
     else
         launch_mutual_shape<2>(tpl, waves, grid, pos, gm, n, nmaj, tl, part, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_mutual(int tpl, int waves, const double* pos, const double* mass,
+                             const double* lam, double cu, int64_t n, double G, double* part,
+                             hipStream_t s)
+{
+    if (n < 1 || n > kMutualMaxN || !mutual_shape_supported(tpl, waves))
+        return hipErrorInvalidValue;
+    const int R = mutual_ranges(n);
+    const dim3 grid((unsigned)((int64_t)R * (R + 1) / 2));
+    const dim3 block((unsigned)(64 * waves));
+    const double gc = G * cu;
+    if (tpl == 1)
+        hipLaunchKernelGGL((k_vjp_mutual<1, 4>), grid, block, 0, s, pos, mass, lam, gc, n, R, part);
+    else if (tpl == 2 && waves == 2)
+        hipLaunchKernelGGL((k_vjp_mutual<2, 2>), grid, block, 0, s, pos, mass, lam, gc, n, R, part);
+    else if (tpl == 2)
+        hipLaunchKernelGGL((k_vjp_mutual<2, 4>), grid, block, 0, s, pos, mass, lam, gc, n, R, part);
+    else
+        hipLaunchKernelGGL((k_vjp_mutual<4, 4>), grid, block, 0, s, pos, mass, lam, gc, n, R, part);
     return hipGetLastError();
 }
 

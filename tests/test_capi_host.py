@@ -164,15 +164,25 @@ def test_tile_table():
     assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == (1, 2, 9, 1)
     assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(1, 2, 9, 3))) == C.NBODY_EINVAL
     # the adjoint pass defaults to scalar operands, 2 waves, up to 64 source
-    # chunks of >= 16 bodies, within the workspace's chunk cap
+    # chunks of >= 16 bodies, within the workspace's chunk cap; from 7,000 to
+    # 131,072 bodies to each pair once in the (2, 4) shape
     for n, want in ((20, (1, 2, 1, 1)), (100, (1, 2, 6, 1)), (2079, (1, 2, 64, 1)),
-                    (131072, (1, 2, 32, 1))):
+                    (6999, (1, 2, 64, 1)), (7000, (2, 4, 1, 5)), (131072, (2, 4, 1, 5)),
+                    (131073, (1, 2, 31, 1))):
         assert lib.nbody_get_tile(1, 0, n, ctypes.byref(t)) == C.NBODY_OK
         assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == want, n
-    # it takes variants 0 (LDS tiles) and 1 (scalar operands) only
+    # it takes variants 0 (LDS tiles), 1 (scalar operands) and 5 (each pair
+    # once, the force pass's shapes, one chunk, up to 131,072 bodies)
     assert lib.nbody_set_tile(1, 0, 100, ctypes.byref(C.Tile(1, 1, 1, 1))) == C.NBODY_OK
     assert lib.nbody_get_tile(1, 0, 100, ctypes.byref(t)) == C.NBODY_OK and t.variant == 1
     assert lib.nbody_set_tile(1, 0, 100, ctypes.byref(C.Tile(1, 1, 1, 2))) == C.NBODY_EINVAL
+    for shape in ((1, 4), (2, 2), (2, 4), (4, 4)):
+        assert lib.nbody_set_tile(1, 0, 5000, ctypes.byref(C.Tile(*shape, 1, 5))) == C.NBODY_OK
+        assert lib.nbody_get_tile(1, 0, 5000, ctypes.byref(t)) == C.NBODY_OK
+        assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == (*shape, 1, 5)
+    assert lib.nbody_set_tile(1, 0, 5000, ctypes.byref(C.Tile(4, 2, 1, 5))) == C.NBODY_EINVAL
+    assert lib.nbody_set_tile(1, 0, 5000, ctypes.byref(C.Tile(2, 4, 2, 5))) == C.NBODY_EINVAL
+    assert lib.nbody_set_tile(1, 0, 131073, ctypes.byref(C.Tile(2, 4, 1, 5))) == C.NBODY_EINVAL
     assert lib.nbody_set_tile(2, 0, 0, ctypes.byref(C.Tile(2, 1, 16, 1))) == C.NBODY_OK
     assert lib.nbody_get_tile(2, 0, 0, ctypes.byref(t)) == C.NBODY_OK and t.variant == 1
     assert lib.nbody_set_tile(3, 0, 10, ctypes.byref(C.Tile(1, 1, 1, 0))) == C.NBODY_EINVAL
@@ -227,7 +237,7 @@ def test_tile_table_single_workgroup_variant():
     for bad in [(2, 4, 4, 5), (1, 4, 2, 5), (1, 8, 1, 5), (1, 2, 1, 5), (4, 1, 1, 5), (4, 2, 1, 5)]:
         assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(*bad))) == C.NBODY_EINVAL, bad
     assert lib.nbody_set_tile(0, 1, 10425, ctypes.byref(C.Tile(4, 4, 1, 5))) == C.NBODY_OK
-    for kind, prec, n in [(1, 0, 10425), (0, 0, 131073), (0, 1, 131073)]:
+    for kind, prec, n in [(1, 0, 131073), (0, 0, 131073), (0, 1, 131073)]:
         assert lib.nbody_set_tile(kind, prec, n, ctypes.byref(C.Tile(1, 4, 1, 5))) == C.NBODY_EINVAL
     # ensembles take it too (a plan with a system of more than 40 ranges falls
     # back to the heuristic tile)

@@ -95,6 +95,46 @@ def test_adjoint_transpose_pass_tiles(vtile, n_small):
     nb.reset_caches()
 
 
+@pytest.mark.parametrize("shape", [(1, 4), (2, 2), (2, 4), (4, 4)])
+@pytest.mark.parametrize("n_small", [20, 150, 300, 1100])
+def test_adjoint_transpose_pass_each_pair_once(shape, n_small):
+    """The transpose-Jacobian pass with each unordered pair once (tile
+    variant 5): one range (20 and 150 small bodies), two and five ranges with
+    a ragged last block (300, 1100), every workgroup shape."""
+    nb.reset_caches()
+    s = S.solar_system(44, n_small, n_major=19)
+    nb.set_tile(1, "fp64", s.n, shape[0], shape[1], 1, 5)
+    assert nb.get_tile(1, "fp64", s.n)["variant"] == 5
+    rng = np.random.default_rng(n_small + shape[0])
+    lr, lv = rng.normal(size=(3, s.n)), rng.normal(size=(3, s.n)) * 10
+    gr, gv, gm = oracle.adjoint(s.pos, s.vel, s.mass, s.G, 0.1, 30, lr, lv)
+    args = (T(s.pos), T(s.vel), T(s.mass), s.G, 0.1, 30, 7, T(lr), T(lv))
+    Gr, Gv, Gm, _, _ = nb.verlet_adjoint(*args)
+    er, ev, em = nrel(H(Gr), gr), nrel(H(Gv), gv), nrel(H(Gm), gm)
+    print(f"n={s.n} shape={shape}: rel err r0 {er:.2e} v0 {ev:.2e} m {em:.2e}", flush=True)
+    assert er <= 1e-10 and ev <= 1e-10 and em <= 1e-10
+    again = nb.verlet_adjoint(*args)
+    assert all(torch.equal(a, b) for a, b in zip(again[:3], (Gr, Gv, Gm)))
+    nb.reset_caches()
+
+
+def test_adjoint_each_pair_once_at_10425_bodies():
+    """The 10,425-body workload, three steps, the pair-once pass in the
+    (2, 4) shape against the oracle's reverse sweep."""
+    nb.reset_caches()
+    s = S.config(1)
+    nb.set_tile(1, "fp64", s.n, 2, 4, 1, 5)
+    rng = np.random.default_rng(7)
+    lr, lv = rng.normal(size=(3, s.n)) * 1e-8, rng.normal(size=(3, s.n)) * 1e-6
+    gr, gv, gm = oracle.adjoint(s.pos, s.vel, s.mass, s.G, s.dt, 3, lr, lv)
+    Gr, Gv, Gm, _, _ = nb.verlet_adjoint(T(s.pos), T(s.vel), T(s.mass), s.G, s.dt, 3, 2,
+                                         T(lr), T(lv))
+    er, ev, em = nrel(H(Gr), gr), nrel(H(Gv), gv), nrel(H(Gm), gm)
+    print(f"n={s.n}: rel err r0 {er:.2e} v0 {ev:.2e} m {em:.2e}", flush=True)
+    assert er <= 1e-10 and ev <= 1e-10 and em <= 1e-10
+    nb.reset_caches()
+
+
 def test_adjoint_autotune_then_parity():
     """The autotuner over the transpose-Jacobian pass's tiles (LDS-staged and
     scalar-operand sources) keeps a supported tile for the size class, and the
@@ -103,7 +143,7 @@ def test_adjoint_autotune_then_parity():
     s = S.solar_system(47, 300, n_major=19)
     tile, ms = nb.autotune(T(s.pos), T(s.mass), s.G, kind=1)
     print(f"autotune adjoint pass n={s.n}: {tile} {ms:.4f} ms", flush=True)
-    assert tile == nb.get_tile(1, "fp64", s.n) and tile["variant"] in (0, 1) and ms > 0
+    assert tile == nb.get_tile(1, "fp64", s.n) and tile["variant"] in (0, 1, 5) and ms > 0
     rng = np.random.default_rng(9)
     lr, lv = rng.normal(size=(3, s.n)), rng.normal(size=(3, s.n)) * 10
     gr, gv, gm = oracle.adjoint(s.pos, s.vel, s.mass, s.G, 0.1, 30, lr, lv)
