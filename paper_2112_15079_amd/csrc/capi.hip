@@ -93,10 +93,10 @@ constexpr int64_t kFusedMax = 16384;
 constexpr int64_t kMutualDefault = 4300;
 constexpr int64_t kMutualSplitDefault = 8500;
 // The adjoint's transpose-Jacobian pass with each pair once, from this size
-// (shape (kVjpMutualTpl, 4); measured: 79.5 against 89.1 us for the one-way
-// pass at 8,000 bodies, 55.7 against 48.9 at 6,000).
+// (shape (kVjpMutualTpl, 4); measured: 76.2 against 89.1 us for the one-way
+// pass at 8,000 bodies, 52.7 against 49.2 at 6,000).
 constexpr int64_t kVjpMutualDefault = 7000;
-constexpr int kVjpMutualTpl = 2;
+constexpr int kVjpMutualTpl = 4;
 
 // The each-pair-once pass serves single systems (FP64 or split) of up to
 // kMutualMaxN bodies: one partial per range of 256 bodies (plus a few for a

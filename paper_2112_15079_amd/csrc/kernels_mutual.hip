@@ -998,9 +998,14 @@ __global__ __launch_bounds__(64 * KMW) void k_vjp_mutual(const double* __restric
                                                          double* __restrict__ part)
 {
     using Shape = MutualShape<KMT, KMW>;
-    __shared__ VSrc S;
+    // the waves' partial sums reuse the staged sources' space once the sweep
+    // is done (36 KB of LDS in all: four workgroups per CU)
+    using Comb = double[Shape::kShare > 1 ? Shape::kShare - 1 : 1][Shape::kSets][KMT][4][64];
+    static_assert(sizeof(Comb) <= sizeof(VSrc), "the sums fit in the sources' space");
+    __shared__ double smem[sizeof(VSrc) / sizeof(double)];
     __shared__ double racc[kMM][4][64];
-    __shared__ double comb[Shape::kShare > 1 ? Shape::kShare - 1 : 1][Shape::kSets][KMT][4][64];
+    VSrc& S = *reinterpret_cast<VSrc*>(smem);
+    Comb& comb = *reinterpret_cast<Comb*>(smem);
 
     const MutualTail whole{R, (int)((int64_t)R * (R + 1) / 2), 0, 0};
     int g, r, half, xslot;

@@ -165,9 +165,9 @@ def test_tile_table():
     assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(1, 2, 9, 3))) == C.NBODY_EINVAL
     # the adjoint pass defaults to scalar operands, 2 waves, up to 64 source
     # chunks of >= 16 bodies, within the workspace's chunk cap; from 7,000 to
-    # 131,072 bodies to each pair once in the (2, 4) shape
+    # 131,072 bodies to each pair once in the (4, 4) shape
     for n, want in ((20, (1, 2, 1, 1)), (100, (1, 2, 6, 1)), (2079, (1, 2, 64, 1)),
-                    (6999, (1, 2, 64, 1)), (7000, (2, 4, 1, 5)), (131072, (2, 4, 1, 5)),
+                    (6999, (1, 2, 64, 1)), (7000, (4, 4, 1, 5)), (131072, (4, 4, 1, 5)),
                     (131073, (1, 2, 31, 1))):
         assert lib.nbody_get_tile(1, 0, n, ctypes.byref(t)) == C.NBODY_OK
         assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == want, n

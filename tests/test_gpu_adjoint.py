@@ -119,11 +119,12 @@ def test_adjoint_transpose_pass_each_pair_once(shape, n_small):
 
 
 def test_adjoint_each_pair_once_at_10425_bodies():
-    """The 10,425-body workload, three steps, the pair-once pass in the
-    (2, 4) shape against the oracle's reverse sweep."""
+    """The 10,425-body workload, three steps, the pair-once pass in its
+    default (4, 4) shape against the oracle's reverse sweep."""
     nb.reset_caches()
     s = S.config(1)
-    nb.set_tile(1, "fp64", s.n, 2, 4, 1, 5)
+    assert nb.get_tile(1, "fp64", s.n) == {"targets_per_lane": 4, "waves": 4, "chunks": 1,
+                                           "variant": 5}
     rng = np.random.default_rng(7)
     lr, lv = rng.normal(size=(3, s.n)) * 1e-8, rng.normal(size=(3, s.n)) * 1e-6
     gr, gv, gm = oracle.adjoint(s.pos, s.vel, s.mass, s.G, s.dt, 3, lr, lv)
