@@ -49,3 +49,35 @@ def test_roofline_counts_twenty_flops_per_ordered_pair():
     # another tile: no counter figures
     r1 = bench.roofline(n, dict(tile, variant=1), ms, 0.038)
     assert "counter_frac_fp64" not in r1 and r1["traffic"] is None
+
+
+def test_oracle_is_used_by_the_cpu_baseline_leg_only():
+    """The oracle is test infrastructure: in bench.py it is imported only by
+    the CPU-baseline leg's functions (all skipped by --no-cpu-baseline), and
+    the package never imports it."""
+    import ast
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    users = set()
+    for fn in ast.walk(tree):
+        if isinstance(fn, ast.FunctionDef):
+            for node in ast.walk(fn):
+                if isinstance(node, ast.Import) and any(a.name == "oracle" for a in node.names):
+                    users.add(fn.name)
+                if isinstance(node, ast.ImportFrom) and node.module == "oracle":
+                    users.add(fn.name)
+    top = [n for n in tree.body if isinstance(n, (ast.Import, ast.ImportFrom))
+           and ("oracle" in [a.name for a in n.names] or getattr(n, "module", None) == "oracle")]
+    assert not top
+    assert users == {"cpu_baseline", "oracle_accel_errors", "oracle_scan_rates"}
+    calls = {n.func.id for n in ast.walk(tree) if isinstance(n, ast.Call)
+             and isinstance(n.func, ast.Name) and n.func.id in users}
+    assert calls == users
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    for name in users:   # every call sits behind the --no-cpu-baseline switch
+        for line in [l for l in src.splitlines() if f"{name}(" in l and "def " not in l]:
+            idx = src.index(line)
+            assert "if not args.no_cpu_baseline" in src[max(0, idx - 400):idx], name
+    pkg = os.path.join(ROOT, "paper_2112_15079_amd")
+    for f in os.listdir(pkg):
+        if f.endswith(".py"):
+            assert "import oracle" not in open(os.path.join(pkg, f)).read(), f
