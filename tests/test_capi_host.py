@@ -357,3 +357,21 @@ def test_target_share_validates_first():
     assert wsb(C.OP_ACCEL_SHARD, 131072, 1, 0, 1, 0) >= 64 * 3 * 131072 * 8 + 131072 * 8
     assert wsb(C.OP_ACCEL_SHARD, 131072, 1, 0, 1, 1) == 0
     assert wsb(C.OP_ACCEL_SHARD, 131072, 2, 0, 1, 0) == 0
+
+
+def test_oracle_and_hip_path_share_no_code():
+    """The oracle and the HIP path are independent: no source of the library
+    (kernels, C ABI, binding, header) names the oracle, and the oracle's
+    sources name nothing of the library."""
+    lib_dirs = [os.path.join(ROOT, "paper_2112_15079_amd", "csrc"),
+                os.path.join(ROOT, "paper_2112_15079_amd"), os.path.join(ROOT, "include")]
+    for d in lib_dirs:
+        for f in os.listdir(d):
+            if f.endswith((".hip", ".hpp", ".h", ".py")):
+                assert "oracle" not in open(os.path.join(d, f)).read().lower(), f
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith((".c", ".h", ".py")):
+            src = open(os.path.join(ROOT, "oracle", f)).read()
+            for name in ("paper_2112_15079_amd", "csrc", "nbody.h", "libnbody", "hip_runtime",
+                         "hipMalloc", "hipLaunch", "__global__"):
+                assert name not in src, (f, name)
