@@ -1,6 +1,7 @@
 // Force pass of Eq. (1) with each unordered pair evaluated once (Newton's
 // third law; tile variant 5): the pair's factor f = |d|^-3 serves both
-// a_i += G m_j f d and a_j -= G m_i f d.  In FP64 that is about 23 vector
+// a_i += G m_j f d and a_j -= G m_i f d.  (The adjoint's transpose-Jacobian
+// pass with the same schedule follows at the end of the file.)  In FP64 that is about 23 vector
 // instructions per unordered pair with four targets per lane, against 2 x 17
 // for the two ordered pairs.
 //
