@@ -376,6 +376,29 @@ def test_mutual_pairs_split_last_round(n):
         assert np.array_equal(H(p1), H(p2)) and np.array_equal(H(v1), H(v2))
 
 
+def test_beyond_the_pair_once_limit_sampled():
+    """160,000 bodies, past the each-pair-once pass's 131,072: the default
+    one-way tiles, FP64 and split, on 256 sampled targets against the
+    oracle, and a 4-step run equal to 2 + 2 steps."""
+    nb.reset_caches()
+    s = S.solar_system(90, 160000 - 31, n_major=30)
+    assert nb.get_tile(0, "fp64", s.n)["variant"] in (0, 1, 2)
+    rng = np.random.default_rng(160)
+    idx = np.unique(np.concatenate([[0, s.n - 1], rng.choice(s.n, 254, replace=False)]))
+    ref = oracle.accel_targets(s.pos, s.mass, s.G, idx)
+    m = T(s.mass)
+    for precision, tol in (("fp64", 1e-13), ("split", 2e-12)):
+        e = rel(H(nb.accel(T(s.pos), m, s.G, precision=precision))[:, idx], ref)
+        log(f"n={s.n} {precision}: sampled rel err {e:.2e}")
+        assert e <= tol
+        p1, v1 = T(s.pos), T(s.vel)
+        nb.verlet_run(p1, v1, m, s.G, 0.1, 4, precision=precision)
+        p2, v2 = T(s.pos), T(s.vel)
+        nb.verlet_run(p2, v2, m, s.G, 0.1, 2, precision=precision)
+        nb.verlet_run(p2, v2, m, s.G, 0.1, 2, precision=precision)
+        assert np.array_equal(H(p1), H(p2)) and np.array_equal(H(v1), H(v2))
+
+
 def test_mutual_pairs_rejected_where_unsupported():
     for tile in MUTUAL:   # beyond 131,072 bodies (512 ranges of partials)
         for precision in ("fp64", "split"):
