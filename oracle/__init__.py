@@ -11,10 +11,17 @@ the Solar System with CPU-based Parallel Methods"):
 * ``verlet``   Eqs. (3)-(4), velocity Verlet taken literally.
 * ``energy``   Sec. 2: conserved total energy as the accuracy measure.
 * ``momenta``  linear / angular momentum, invariants of Eq. (1).
+* ``accel_targets``  Eq. (1) for a list of targets.
 * ``euler``    the first-order scheme of Sec. 2 (negative control).
+* ``rk4``      the classical fourth-order Runge-Kutta method Sec. 2 names.
 * ``vjp``      Jacobian-transpose of Eq. (1) from its blocks.
 * ``adjoint``  reverse mode through the literal Eqs. (3)-(4) map.
 * ``tangent``  forward mode (dual numbers) through the same map.
+
+Each function is pinned by ``tests/test_oracle.py`` and
+``tests/test_oracle_mutations.py`` to something other than itself (closed
+forms, invariants, extended precision, worked examples, finite differences,
+independent derivations); none is left unpinned.
 
 All arrays are float64 structure-of-arrays: ``pos[3, n]``, ``vel[3, n]``,
 ``mass[n]``.  The C source is ``oracle.c``; :func:`build` compiles it with gcc

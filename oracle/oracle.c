@@ -9,18 +9,25 @@
  *
  * What it follows:
  *   accel      Eq. (1): a_p = sum_{j != p} G m_j (r_j - r_p) / |r_j - r_p|^3,
- *              terms in ascending j, compensated accumulation.
+ *              terms in ascending j, compensated accumulation (accel_targets:
+ *              the same sum for a list of targets).
  *   verlet     Eqs. (3)-(4), velocity Verlet, taken literally, one force
  *              evaluation per step (a_{i+1} is kept as the next a_i).
  *   energy     Sec. 2: total energy (kinetic + pair potential) is the accuracy
  *              measure of a run.
  *   momenta    total linear and angular momentum (invariants of Eq. (1)).
  *   euler      the first-order scheme Sec. 2 rejects (negative control only).
+ *   rk4        the classical fourth-order Runge-Kutta method Sec. 2 names as
+ *              the alternative to velocity Verlet.
  *   vjp        the transpose of the Jacobian of Eq. (1) applied to a
  *              cotangent, from the Jacobian blocks written out one by one.
  *   adjoint    reverse-mode chain rule through the literal Eqs. (3)-(4) map.
  *   tangent    forward-mode derivative of the literal Eqs. (3)-(4) map, by
  *              dual numbers carried through every arithmetic operation.
+ *
+ * Every function is pinned by the CPU tests to something other than itself
+ * (closed forms, invariants, extended precision, worked examples, finite
+ * differences, other derivations); none is left unpinned.
  *
  * Layout: structure of arrays, pos[0..n) = x, pos[n..2n) = y, pos[2n..3n) = z,
  * likewise vel, acc and the cotangents; mass[0..n).  All double precision.
