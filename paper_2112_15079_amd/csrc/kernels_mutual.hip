@@ -110,6 +110,22 @@ __device__ __forceinline__ float row_next32(float x)
                                                               0xF, 0xF, true));
 }
 
+// A source block in LDS: four groups of 16 sources; group grp holds the x,
+// y, z and G m planes of 32 entries each (its 16 sources twice in a row) at
+// kGrp * grp + 32 * plane, so that one base address with immediate offsets
+// reaches all four planes of a group.
+constexpr int kGrp = 128;
+constexpr int kSrcBlock = 4 * kGrp;
+
+__device__ __forceinline__ void stage_source(double* __restrict__ sb, int lane, const Body& b)
+{
+    const int a0 = kGrp * (lane >> 4) + (lane & 15);
+    sb[a0] = b.x; sb[a0 + 16] = b.x;
+    sb[a0 + 32] = b.y; sb[a0 + 48] = b.y;
+    sb[a0 + 64] = b.z; sb[a0 + 80] = b.z;
+    sb[a0 + 96] = b.gm; sb[a0 + 112] = b.gm;
+}
+
 // The FP32 form of tile_sweep (light targets, light sources): per target the
 // 16 terms of a sub-phase are summed in FP32 and the sum is added to the
 // FP64 accumulator; the reaction of a row travels as FP32 and its 16-term sum
@@ -136,9 +152,9 @@ __device__ __forceinline__ void tile_sweep32(const double* __restrict__ sx,
         float rx = 0.f, ry = 0.f, rz = 0.f;
 #pragma unroll 4
         for (int k = 0; k < 16; ++k) {
-            const int jj = 32 * grp + col + k;
+            const int jj = kGrp * grp + col + k;
             const double jx = sx[jj], jy = sy[jj], jz = sz[jj];
-            const float jg = sgf[jj];
+            const float jg = sgf[32 * grp + col + k];
 #pragma unroll
             for (int t = 0; t < KMT; ++t) {
                 if (t > NSYM || (t == NSYM && !DIAG)) continue;
@@ -234,7 +250,7 @@ __device__ __forceinline__ void tile_sweep_comp(const double* __restrict__ sx,
         k3_zero(kr);
 #pragma unroll 2
         for (int k = 0; k < 16; ++k) {
-            const int jj = 32 * grp + col + k;
+            const int jj = kGrp * grp + col + k;
             const double jx = sx[jj], jy = sy[jj], jz = sz[jj], jg = sg[jj];
             const bool jheavy = MIXED && jbase + 16 * grp + ((col + k) & 15) < n_major;
 #pragma unroll
@@ -308,7 +324,7 @@ __device__ __forceinline__ void tile_sweep_comp(const double* __restrict__ sx,
 
 // One tile sweep: the KMT targets of this lane (target blocks I0 .. I0+KMT-1)
 // against one source block J staged in LDS as four groups of 16 sources,
-// each stored twice in a row (s*[32*grp + i], i < 32).  Targets t < NSYM lie
+// each stored twice in a row (s*[kGrp*grp + i], i < 32).  Targets t < NSYM lie
 // below J (both directions), target NSYM is J itself if DIAG (one direction,
 // without the self pair), the rest lie above J (nothing to do).  Lane (row R,
 // column c) pairs with source 16*grp + (c + k) mod 16 at step k of sub-phase
@@ -335,7 +351,7 @@ __device__ __forceinline__ void tile_sweep(const double* __restrict__ sx,
         double rx = 0.0, ry = 0.0, rz = 0.0;
 #pragma unroll 4
         for (int k = 0; k < 16; ++k) {
-            const int jj = 32 * grp + col + k;
+            const int jj = kGrp * grp + col + k;
             const double jx = sx[jj], jy = sy[jj], jz = sz[jj], jg = sg[jj];
 #pragma unroll
             for (int t = 0; t < KMT; ++t) {
@@ -539,9 +555,8 @@ __device__ __forceinline__ void mutual_half_body(const double* __restrict__ pos,
                                                  const double* __restrict__ gm, int64_t n,
                                                  int64_t n_major, int g, int r, int half,
                                                  int xslot, double* __restrict__ part,
-                                                 double (*sx)[128], double (*sy)[128],
-                                                 double (*sz)[128], double (*sg)[128],
-                                                 float (*sgf)[128], double (*racc)[3][64],
+                                                 double (*src)[kSrcBlock], float (*sgf)[128],
+                                                 double (*racc)[3][64],
                                                  double* combp)
 {
     constexpr int KT = 2;
@@ -566,12 +581,9 @@ __device__ __forceinline__ void mutual_half_body(const double* __restrict__ pos,
     }
     {
         const Body b = load_body(pos, gm, n, n, (int64_t)J * 64 + lane);
-        const int a0 = 32 * (lane >> 4) + (lane & 15);
-        sx[w][a0] = b.x; sx[w][a0 + 16] = b.x;
-        sy[w][a0] = b.y; sy[w][a0 + 16] = b.y;
-        sz[w][a0] = b.z; sz[w][a0 + 16] = b.z;
-        sg[w][a0] = b.gm; sg[w][a0 + 16] = b.gm;
+        stage_source(src[w], lane, b);
         if (SPLIT) {
+            const int a0 = 32 * (lane >> 4) + (lane & 15);
             sgf[w][a0] = (float)b.gm;
             sgf[w][a0 + 16] = (float)b.gm;
         }
@@ -583,14 +595,17 @@ __device__ __forceinline__ void mutual_half_body(const double* __restrict__ pos,
     __syncthreads();
     if (PREC == 2) {
         if (J < nb)
-            sweep_comp<KT>(fp32, J - I0, I0, J, lane, sx[w], sy[w], sz[w], sg[w], &racc[w][0][0], tg,
+            sweep_comp<KT>(fp32, J - I0, I0, J, lane, src[w], src[w] + 32, src[w] + 64,
+                           src[w] + 96, &racc[w][0][0], tg,
                            n_major, ax, ay, az, ka);
     } else if (J < nb) {   // r > g: J - I0 >= 2, every tile both ways
         if (fp32)
-            sweep_dispatch32<KT>(J - I0, sx[w], sy[w], sz[w], sgf[SPLIT ? w : 0], &racc[w][0][0],
+            sweep_dispatch32<KT>(J - I0, src[w], src[w] + 32, src[w] + 64, sgf[SPLIT ? w : 0],
+                                 &racc[w][0][0],
                                  lane, tg, tgf, ax, ay, az);
         else
-            sweep_dispatch<KT>(J - I0, sx[w], sy[w], sz[w], sg[w], &racc[w][0][0], lane, tg, ax,
+            sweep_dispatch<KT>(J - I0, src[w], src[w] + 32, src[w] + 64, src[w] + 96, &racc[w][0][0],
+                               lane, tg, ax,
                                ay, az, PolyConst{vreg_const(1.875), vreg_const(1.5)});
     }
     if (PREC == 2) {
@@ -656,14 +671,14 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
 {
     using Shape = MutualShape<KMT, KMW>;
     constexpr bool SPLIT = PREC == 1;   // the FP32 tiles (light sources' G m as floats)
-    __shared__ double sx[kMM][128], sy[kMM][128], sz[kMM][128], sg[kMM][128];
+    __shared__ double src[kMM][kSrcBlock];
     __shared__ float sgf[SPLIT ? kMM : 1][128];
     __shared__ double racc[kMM][3][64];
     __shared__ double comb[Shape::kShare > 1 ? Shape::kShare - 1 : 1][Shape::kSets][KMT][3][64];
     if constexpr (KMT == 4 && KMW == 4) {
         static_assert(sizeof(comb) >= 3 * 2 * 3 * 64 * sizeof(double), "half-pair sums fit");
         if (half >= 0) {
-            mutual_half_body<PREC>(pos, gm, n, n_major, g, r, half, xslot, part, sx, sy, sz, sg,
+            mutual_half_body<PREC>(pos, gm, n, n_major, g, r, half, xslot, part, src,
                                     SPLIT ? sgf : nullptr, racc, &comb[0][0][0][0][0]);
             return;
         }
@@ -693,12 +708,9 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
     for (int jb = w; jb < kMM; jb += KMW) {
         const int64_t j = (int64_t)(J0 + jb) * 64 + lane;
         const Body b = load_body(pos, gm, n, stride, j);
-        const int a0 = 32 * (lane >> 4) + (lane & 15);
-        sx[jb][a0] = b.x; sx[jb][a0 + 16] = b.x;
-        sy[jb][a0] = b.y; sy[jb][a0 + 16] = b.y;
-        sz[jb][a0] = b.z; sz[jb][a0 + 16] = b.z;
-        sg[jb][a0] = b.gm; sg[jb][a0 + 16] = b.gm;
+        stage_source(src[jb], lane, b);
         if (SPLIT) {
+            const int a0 = 32 * (lane >> 4) + (lane & 15);
             sgf[jb][a0] = (float)b.gm;
             sgf[jb][a0 + 16] = (float)b.gm;
         }
@@ -719,7 +731,8 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
             const int jb = (w + p) % kMM;
             const int J = J0 + jb;
             if (J < nb && J >= I0)
-                sweep_comp<KMT>(fp32, J - I0, I0, J, lane, sx[jb], sy[jb], sz[jb], sg[jb],
+                sweep_comp<KMT>(fp32, J - I0, I0, J, lane, src[jb], src[jb] + 32, src[jb] + 64,
+                                src[jb] + 96,
                                 &racc[jb][0][0], tg, n_major, ax, ay, az, ka);
             __syncthreads();
         }
@@ -734,7 +747,7 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
             const int jb = (w + p) % kMM;
             const int J = J0 + jb;
             if (J < nb && J >= I0)
-                sweep_dispatch32<KMT>(J - I0, sx[jb], sy[jb], sz[jb], sgf[SPLIT ? jb : 0],
+                sweep_dispatch32<KMT>(J - I0, src[jb], src[jb] + 32, src[jb] + 64, sgf[SPLIT ? jb : 0],
                                       &racc[jb][0][0], lane, tg, tgf, ax, ay, az);
             __syncthreads();
         }
@@ -744,7 +757,8 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
             const int jb = (w + p) % kMM;
             const int J = J0 + jb;
             if (J < nb && J >= I0)
-                sweep_dispatch<KMT>(J - I0, sx[jb], sy[jb], sz[jb], sg[jb], &racc[jb][0][0],
+                sweep_dispatch<KMT>(J - I0, src[jb], src[jb] + 32, src[jb] + 64, src[jb] + 96,
+                                    &racc[jb][0][0],
                                     lane, tg, ax, ay, az, c);
             __syncthreads();
         }
@@ -897,9 +911,14 @@ __device__ __forceinline__ VBody load_vbody(const double* __restrict__ pos,
     return b;
 }
 
-struct VSrc {   // the staged source blocks: seven planes, groups of 16 doubled
-    double x[kMM][128], y[kMM][128], z[kMM][128], m[kMM][128], ux[kMM][128], uy[kMM][128],
-        uz[kMM][128];
+// The staged source blocks: per block four groups of 16 sources; group grp
+// holds the planes x, y, z, m, ux, uy, uz of 32 entries each (its 16 sources
+// twice in a row) at kVGrp * grp + 32 * plane, one base address with
+// immediate offsets for all seven.
+constexpr int kVGrp = 7 * 32;
+
+struct VSrc {
+    double s[kMM][4 * kVGrp];
 };
 
 struct VAcc {
@@ -922,9 +941,9 @@ __device__ __forceinline__ void vjp_tile(const VSrc& S, int jb, double* __restri
         double rx = 0.0, ry = 0.0, rz = 0.0, rg = 0.0;
 #pragma unroll 2
         for (int k = 0; k < 16; ++k) {
-            const int jj = 32 * grp + col + k;
-            const double jx = S.x[jb][jj], jy = S.y[jb][jj], jz = S.z[jb][jj], jm = S.m[jb][jj];
-            const double jux = S.ux[jb][jj], juy = S.uy[jb][jj], juz = S.uz[jb][jj];
+            const double* sj = &S.s[jb][kVGrp * grp + col + k];
+            const double jx = sj[0], jy = sj[32], jz = sj[64], jm = sj[96];
+            const double jux = sj[128], juy = sj[160], juz = sj[192];
 #pragma unroll
             for (int t = 0; t < KMT; ++t) {
                 if (t > NSYM || (t == NSYM && !DIAG)) continue;
@@ -1030,14 +1049,13 @@ __global__ __launch_bounds__(64 * KMW) void k_vjp_mutual(const double* __restric
     }
     for (int jb = w; jb < kMM; jb += KMW) {
         const VBody b = load_vbody(pos, mass, lam, n, (int64_t)(J0 + jb) * 64 + lane);
-        const int a0 = 32 * (lane >> 4) + (lane & 15);
-        S.x[jb][a0] = b.x; S.x[jb][a0 + 16] = b.x;
-        S.y[jb][a0] = b.y; S.y[jb][a0 + 16] = b.y;
-        S.z[jb][a0] = b.z; S.z[jb][a0 + 16] = b.z;
-        S.m[jb][a0] = b.m; S.m[jb][a0 + 16] = b.m;
-        S.ux[jb][a0] = b.ux; S.ux[jb][a0 + 16] = b.ux;
-        S.uy[jb][a0] = b.uy; S.uy[jb][a0 + 16] = b.uy;
-        S.uz[jb][a0] = b.uz; S.uz[jb][a0 + 16] = b.uz;
+        double* sb = &S.s[jb][kVGrp * (lane >> 4) + (lane & 15)];
+        const double v[7] = {b.x, b.y, b.z, b.m, b.ux, b.uy, b.uz};
+#pragma unroll
+        for (int pl = 0; pl < 7; ++pl) {
+            sb[32 * pl] = v[pl];
+            sb[32 * pl + 16] = v[pl];
+        }
         for (int k = 0; k < 4; ++k) racc[jb][k][lane] = 0.0;
     }
     __syncthreads();
