@@ -674,12 +674,17 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
     __shared__ double src[kMM][kSrcBlock];
     __shared__ float sgf[SPLIT ? kMM : 1][128];
     __shared__ double racc[kMM][3][64];
-    __shared__ double comb[Shape::kShare > 1 ? Shape::kShare - 1 : 1][Shape::kSets][KMT][3][64];
+    // the range's target blocks at the start, the waves' target sums at the end
+    constexpr int kCombD = (Shape::kShare > 1 ? Shape::kShare - 1 : 1) * Shape::kSets * KMT * 3 * 64;
+    constexpr int kTgtD = kMM * 4 * 64;
+    __shared__ double cbuf[kCombD > kTgtD ? kCombD : kTgtD];
+    double (*comb)[Shape::kSets][KMT][3][64] =
+        reinterpret_cast<double (*)[Shape::kSets][KMT][3][64]>(cbuf);
     if constexpr (KMT == 4 && KMW == 4) {
-        static_assert(sizeof(comb) >= 3 * 2 * 3 * 64 * sizeof(double), "half-pair sums fit");
+        static_assert(sizeof(cbuf) >= 3 * 2 * 3 * 64 * sizeof(double), "half-pair sums fit");
         if (half >= 0) {
             mutual_half_body<PREC>(pos, gm, n, n_major, g, r, half, xslot, part, src,
-                                    SPLIT ? sgf : nullptr, racc, &comb[0][0][0][0][0]);
+                                    SPLIT ? sgf : nullptr, racc, cbuf);
             return;
         }
     }
@@ -693,21 +698,26 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
     const int J0 = r * kMM;               // the workgroup's source blocks J0 .. J0 + 3
     const int64_t plane = 3 * stride;
 
-    Body tg[KMT];
     double ax[KMT], ay[KMT], az[KMT];
     Kahan3 ka[KMT];
 #pragma unroll
     for (int t = 0; t < KMT; ++t) {
-        tg[t] = load_body(pos, gm, n, stride, (int64_t)(I0 + t) * 64 + lane);
         ax[t] = 0.0; ay[t] = 0.0; az[t] = 0.0;
         k3_zero(ka[t]);
     }
 
-    // stage the source blocks (wave w: blocks w, w + KMW, ...): four groups
-    // of 16, each twice in a row
+    // stage the range's target blocks and its source blocks (wave w: blocks
+    // w, w + KMW, ...): the targets as planes of 64, the sources in four
+    // groups of 16, each twice in a row.  Each wave then reads its own target
+    // blocks from LDS: one global load of a body per workgroup, not per wave.
+    double (*tst)[4][64] = reinterpret_cast<double (*)[4][64]>(cbuf);
     for (int jb = w; jb < kMM; jb += KMW) {
-        const int64_t j = (int64_t)(J0 + jb) * 64 + lane;
-        const Body b = load_body(pos, gm, n, stride, j);
+        const Body a = load_body(pos, gm, n, stride, (int64_t)(g * kMM + jb) * 64 + lane);
+        const Body b = load_body(pos, gm, n, stride, (int64_t)(J0 + jb) * 64 + lane);
+        tst[jb][0][lane] = a.x;
+        tst[jb][1][lane] = a.y;
+        tst[jb][2][lane] = a.z;
+        tst[jb][3][lane] = a.gm;
         stage_source(src[jb], lane, b);
         if (SPLIT) {
             const int a0 = 32 * (lane >> 4) + (lane & 15);
@@ -718,13 +728,18 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
         racc[jb][1][lane] = 0.0;
         racc[jb][2][lane] = 0.0;
     }
-    float tgf[KMT];
-#pragma unroll
-    for (int t = 0; t < KMT; ++t) tgf[t] = (float)tg[t].gm;
     // split form: waves whose target blocks start below the first block
     // free of heavy bodies stay in FP64
     const bool fp32 = PREC != 0 && I0 >= (int)((n_major + 63) / 64);
     __syncthreads();
+    Body tg[KMT];
+    float tgf[KMT];
+#pragma unroll
+    for (int t = 0; t < KMT; ++t) {
+        const int tb = set * KMT + t;
+        tg[t] = Body{tst[tb][0][lane], tst[tb][1][lane], tst[tb][2][lane], tst[tb][3][lane]};
+        tgf[t] = (float)tg[t].gm;
+    }
 
     if constexpr (PREC == 2) {
         for (int p = 0; p < Shape::kPhases; ++p) {
