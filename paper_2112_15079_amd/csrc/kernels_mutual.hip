@@ -7,8 +7,9 @@
 //
 // Bodies are cut into blocks of 64 and the blocks into "ranges" of kMM = 4.
 // Workgroup (g, r), r >= g, takes range g as its targets and range r as its
-// sources, whose four blocks it stages in LDS.  Each of its KMW waves holds
-// KMT target blocks of range g (one body of each per lane); see MutualShape
+// sources and stages the four blocks of each in LDS (each body loaded once
+// per workgroup).  Each of its KMW waves then holds KMT target blocks of
+// range g in registers (one body of each per lane); see MutualShape
 // for how the waves split the (target block, source block) tiles between
 // them.  In phase p wave w works on source block (w + p) mod 4, so in every
 // phase the waves touch different source blocks.
