@@ -1056,14 +1056,25 @@ __global__ __launch_bounds__(64 * KMW) void k_vjp_mutual(const double* __restric
     const int J0 = r * kMM;
     const int64_t plane = 4 * n;
 
+    // shape (4, 4): the four waves hold the same four target blocks, so the
+    // range's targets are staged in LDS too (each body loaded once per
+    // workgroup, not once per wave); the other shapes load their own
+    constexpr bool kShareTargets = KMT == 4 && KMW == 4;
+    __shared__ double tst[kShareTargets ? kMM : 1][7][64];
     VBody tg[KMT];
     VAcc o[KMT];
 #pragma unroll
     for (int t = 0; t < KMT; ++t) {
-        tg[t] = load_vbody(pos, mass, lam, n, (int64_t)(I0 + t) * 64 + lane);
+        if (!kShareTargets) tg[t] = load_vbody(pos, mass, lam, n, (int64_t)(I0 + t) * 64 + lane);
         o[t] = VAcc{0.0, 0.0, 0.0, 0.0};
     }
     for (int jb = w; jb < kMM; jb += KMW) {
+        if (kShareTargets) {
+            const VBody a = load_vbody(pos, mass, lam, n, (int64_t)(g * kMM + jb) * 64 + lane);
+            const double v[7] = {a.x, a.y, a.z, a.m, a.ux, a.uy, a.uz};
+#pragma unroll
+            for (int pl = 0; pl < 7; ++pl) tst[jb][pl][lane] = v[pl];
+        }
         const VBody b = load_vbody(pos, mass, lam, n, (int64_t)(J0 + jb) * 64 + lane);
         double* sb = &S.s[jb][kVGrp * (lane >> 4) + (lane & 15)];
         const double v[7] = {b.x, b.y, b.z, b.m, b.ux, b.uy, b.uz};
@@ -1075,6 +1086,14 @@ __global__ __launch_bounds__(64 * KMW) void k_vjp_mutual(const double* __restric
         for (int k = 0; k < 4; ++k) racc[jb][k][lane] = 0.0;
     }
     __syncthreads();
+    if (kShareTargets) {
+#pragma unroll
+        for (int t = 0; t < KMT; ++t) {
+            const int tb = set * KMT + t;
+            tg[t] = VBody{tst[tb][0][lane], tst[tb][1][lane], tst[tb][2][lane], tst[tb][3][lane],
+                          tst[tb][4][lane], tst[tb][5][lane], tst[tb][6][lane]};
+        }
+    }
     for (int p = 0; p < Shape::kPhases; ++p) {
         const int jb = (w + p) % kMM;
         const int J = J0 + jb;
