@@ -59,6 +59,12 @@
 #include "common.hpp"
 #include "pair_math.hpp"
 
+// Marks for the test instruments (tests/host), which define the macro
+// before including this file; in the library it expands to nothing.
+#ifndef NB_MUTUAL_MARK
+#define NB_MUTUAL_MARK(k)
+#endif
+
 namespace nb {
 namespace {
 
@@ -594,6 +600,7 @@ __device__ __forceinline__ void mutual_half_body(const double* __restrict__ pos,
     }
     const bool fp32 = PREC != 0 && I0 >= (int)((n_major + 63) / 64);
     __syncthreads();
+    NB_MUTUAL_MARK(1);
     if (PREC == 2) {
         if (J < nb)
             sweep_comp<KT>(fp32, J - I0, I0, J, lane, src[w], src[w] + 32, src[w] + 64,
@@ -609,6 +616,7 @@ __device__ __forceinline__ void mutual_half_body(const double* __restrict__ pos,
                                lane, tg, ax,
                                ay, az, PolyConst{vreg_const(1.875), vreg_const(1.5)});
     }
+    NB_MUTUAL_MARK(2);
     if (PREC == 2) {
 #pragma unroll
         for (int t = 0; t < KT; ++t) {
@@ -733,6 +741,7 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
     // free of heavy bodies stay in FP64
     const bool fp32 = PREC != 0 && I0 >= (int)((n_major + 63) / 64);
     __syncthreads();
+    NB_MUTUAL_MARK(1);   // sources and targets staged, the sweep begins
     Body tg[KMT];
     float tgf[KMT];
 #pragma unroll
@@ -780,6 +789,7 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
         }
     }
 
+    NB_MUTUAL_MARK(2);   // the sweep done
     if (Shape::kShare > 1) {
         // the target sums of the waves sharing a set (one buffer per set and
         // rank), added in wave order
