@@ -47,15 +47,16 @@
 // period per ceil(pairs / 256) rounds of workgroups, one per CU per round.
 // When the pairs past the last whole round are few (at most 128), those
 // pairs are each run as two workgroups of half the work, so the partly
-// filled round costs half a period: a half holds two of the four target
-// blocks (two per lane) against all four source blocks, one per wave.  The
-// halves' targets are disjoint; their reactions on the same sources are
-// not, so the second half writes them to an extra slot.  The split pairs
+// filled round costs half a period: a half holds all four target blocks
+// (four per lane) against all four source blocks, one per wave, over two
+// of the four sub-phases (0-1, 2-3), at the whole pair's cost per pair.
+// Both halves reach every target and every source, so the second half
+// writes its target sums and its reactions to extra slots.  The split pairs
 // are those on the super-diagonals r - g = 1 .. D - 1 and the first kD of
-// r - g = D; the extra slot of pair (g, g + d) is R + d - 1, and the
-// diagonal workgroup of each range writes zeros to the extra slots that no
-// split pair fills, so every body still receives each of its R + D slots
-// exactly once.
+// r - g = D; the extra slots of pair (g, g + d) are R + d - 1 (reactions)
+// and R + D + d - 1 (targets), and the diagonal workgroup of each range
+// writes zeros to the extra slots that no split pair fills, so every body
+// still receives each of its R + 2D slots exactly once.
 #include "common.hpp"
 #include "pair_math.hpp"
 
@@ -137,7 +138,7 @@ __device__ __forceinline__ void stage_source(double* __restrict__ sb, int lane, 
 // 16 terms of a sub-phase are summed in FP32 and the sum is added to the
 // FP64 accumulator; the reaction of a row travels as FP32 and its 16-term sum
 // is added to the FP64 reaction sums in LDS.
-template <int KMT, int NSYM, bool DIAG>
+template <int KMT, int NSYM, bool DIAG, int Q0 = 0, int Q1 = 4>
 __device__ __forceinline__ void tile_sweep32(const double* __restrict__ sx,
                                              const double* __restrict__ sy,
                                              const double* __restrict__ sz,
@@ -150,7 +151,7 @@ __device__ __forceinline__ void tile_sweep32(const double* __restrict__ sx,
     constexpr bool kReact = NSYM > 0;
     const int row = lane >> 4;
     const int col = lane & 15;
-    for (int q = 0; q < 4; ++q) {
+    for (int q = Q0; q < Q1; ++q) {
         const int grp = (row + q) & 3;
         const int home = 16 * grp + col;
         float bx[KMT], by[KMT], bz[KMT];
@@ -235,7 +236,7 @@ __device__ __forceinline__ void k3_zero(Kahan3& k)
 // and only the FP32 sums are kept.  The target sums (ka) run over the whole
 // sweep of the workgroup; each reaction's (16 targets of a row) is added to
 // the FP64 reaction sums in LDS as s - c.  Tile geometry as tile_sweep.
-template <int KMT, int NSYM, bool DIAG, bool MIXED>
+template <int KMT, int NSYM, bool DIAG, bool MIXED, int Q0 = 0, int Q1 = 4>
 __device__ __forceinline__ void tile_sweep_comp(const double* __restrict__ sx,
                                                 const double* __restrict__ sy,
                                                 const double* __restrict__ sz,
@@ -249,7 +250,7 @@ __device__ __forceinline__ void tile_sweep_comp(const double* __restrict__ sx,
     constexpr bool kReact = NSYM > 0;
     const int row = lane >> 4;
     const int col = lane & 15;
-    for (int q = 0; q < 4; ++q) {
+    for (int q = Q0; q < Q1; ++q) {
         const int grp = (row + q) & 3;
         const int home = 16 * grp + col;
         double rx = 0.0, ry = 0.0, rz = 0.0;
@@ -339,7 +340,7 @@ __device__ __forceinline__ void tile_sweep_comp(const double* __restrict__ sx,
 // (DPP, no LDS round trip) and after 16 steps is added to the block's
 // reaction sums in LDS (`ra`, three planes of 64).  Rows work on different
 // groups, so these adds never collide.
-template <int KMT, int NSYM, bool DIAG>
+template <int KMT, int NSYM, bool DIAG, int Q0 = 0, int Q1 = 4>
 __device__ __forceinline__ void tile_sweep(const double* __restrict__ sx,
                                            const double* __restrict__ sy,
                                            const double* __restrict__ sz,
@@ -352,7 +353,7 @@ __device__ __forceinline__ void tile_sweep(const double* __restrict__ sx,
     constexpr bool kReact = NSYM > 0;
     const int row = lane >> 4;
     const int col = lane & 15;
-    for (int q = 0; q < 4; ++q) {
+    for (int q = Q0; q < Q1; ++q) {
         const int grp = (row + q) & 3;
         const int home = 16 * grp + col;     // the source this lane starts (and ends) with
         double rx = 0.0, ry = 0.0, rz = 0.0;
@@ -554,40 +555,52 @@ __host__ __device__ inline void mt_decode(const MutualTail& tl, int64_t bid, int
     xslot = 0;
 }
 
-// Half `half` of the split pair (g, r), r > g: target blocks 4g + 2 half and
-// 4g + 2 half + 1 (two per lane) against source block 4r + w in wave w.  The
-// LDS arrays are the whole-pair workgroup's (same sizes or larger).
-template <int PREC>
+// Whether range pair (g, g + d), 1 <= d <= D, is split into halves.
+__host__ __device__ inline bool mt_is_split(const MutualTail& tl, int g, int d)
+{
+    return g >= 0 && g + d <= tl.R - 1 && (d < tl.D || g < tl.kD);
+}
+
+// Half `half` of the split pair (g, r), r > g, by sub-phases: the four
+// target blocks of range g (four per lane) against source block 4r + w in
+// wave w, over sub-phases Q0 .. Q1 - 1 (half 0: 0 and 1, half 1: 2 and 3),
+// so each half has the whole pair's per-pair cost and half its tiles.  Both
+// halves reach every target and every source: half 0 writes the targets'
+// sums to slot r and the reactions to slot g, half 1 to the extra slots
+// R + D + d - 1 and R + d - 1 (xslot).  The LDS arrays are the whole pair's.
+template <int PREC, int Q0, int Q1>
 __device__ __forceinline__ void mutual_half_body(const double* __restrict__ pos,
                                                  const double* __restrict__ gm, int64_t n,
-                                                 int64_t n_major, int g, int r, int half,
-                                                 int xslot, double* __restrict__ part,
+                                                 int64_t n_major, const MutualTail& tl, int g,
+                                                 int r, int xslot, double* __restrict__ part,
                                                  double (*src)[kSrcBlock], float (*sgf)[128],
-                                                 double (*racc)[3][64],
-                                                 double* combp)
+                                                 double (*racc)[3][64], double* cbuf)
 {
-    constexpr int KT = 2;
-    constexpr bool SPLIT = PREC == 1;   // the FP32 tiles (light sources' G m as floats)
+    constexpr int KMT = 4;
+    constexpr bool SPLIT = PREC == 1;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int nb = (int)((n + 63) / 64);
-    const int I0 = g * kMM + 2 * half;
+    const int I0 = g * kMM;
     const int J = r * kMM + w;
     const int64_t plane = 3 * n;
 
-    Body tg[KT];
-    float tgf[KT];
-    double ax[KT], ay[KT], az[KT];
-    Kahan3 ka[KT];
+    double ax[KMT], ay[KMT], az[KMT];
+    Kahan3 ka[KMT];
 #pragma unroll
-    for (int t = 0; t < KT; ++t) {
-        tg[t] = load_body(pos, gm, n, n, (int64_t)(I0 + t) * 64 + lane);
-        tgf[t] = (float)tg[t].gm;
+    for (int t = 0; t < KMT; ++t) {
         ax[t] = 0.0; ay[t] = 0.0; az[t] = 0.0;
         k3_zero(ka[t]);
     }
+    // wave w stages target block I0 + w and source block J
+    double (*tst)[4][64] = reinterpret_cast<double (*)[4][64]>(cbuf);
     {
+        const Body a = load_body(pos, gm, n, n, (int64_t)(I0 + w) * 64 + lane);
         const Body b = load_body(pos, gm, n, n, (int64_t)J * 64 + lane);
+        tst[w][0][lane] = a.x;
+        tst[w][1][lane] = a.y;
+        tst[w][2][lane] = a.z;
+        tst[w][3][lane] = a.gm;
         stage_source(src[w], lane, b);
         if (SPLIT) {
             const int a0 = 32 * (lane >> 4) + (lane & 15);
@@ -601,55 +614,76 @@ __device__ __forceinline__ void mutual_half_body(const double* __restrict__ pos,
     const bool fp32 = PREC != 0 && I0 >= (int)((n_major + 63) / 64);
     __syncthreads();
     NB_MUTUAL_MARK(1);
-    if (PREC == 2) {
-        if (J < nb)
-            sweep_comp<KT>(fp32, J - I0, I0, J, lane, src[w], src[w] + 32, src[w] + 64,
-                           src[w] + 96, &racc[w][0][0], tg,
-                           n_major, ax, ay, az, ka);
-    } else if (J < nb) {   // r > g: J - I0 >= 2, every tile both ways
-        if (fp32)
-            sweep_dispatch32<KT>(J - I0, src[w], src[w] + 32, src[w] + 64, sgf[SPLIT ? w : 0],
-                                 &racc[w][0][0],
-                                 lane, tg, tgf, ax, ay, az);
-        else
-            sweep_dispatch<KT>(J - I0, src[w], src[w] + 32, src[w] + 64, src[w] + 96, &racc[w][0][0],
-                               lane, tg, ax,
-                               ay, az, PolyConst{vreg_const(1.875), vreg_const(1.5)});
+    Body tg[KMT];
+    float tgf[KMT];
+#pragma unroll
+    for (int t = 0; t < KMT; ++t) {
+        tg[t] = Body{tst[t][0][lane], tst[t][1][lane], tst[t][2][lane], tst[t][3][lane]};
+        tgf[t] = (float)tg[t].gm;
+    }
+    if (J < nb) {   // r > g: J - I0 >= 4, every tile both ways
+        const double* sb = src[w];
+        if constexpr (PREC == 2) {
+            bool th[KMT];
+#pragma unroll
+            for (int t = 0; t < KMT; ++t) th[t] = (int64_t)(I0 + t) * 64 + lane < n_major;
+            if (fp32)
+                tile_sweep_comp<KMT, KMT, false, false, Q0, Q1>(sb, sb + 32, sb + 64, sb + 96,
+                                                                &racc[w][0][0], lane, tg, th,
+                                                                (int64_t)J * 64, n_major, ax, ay,
+                                                                az, ka);
+            else
+                tile_sweep_comp<KMT, KMT, false, true, Q0, Q1>(sb, sb + 32, sb + 64, sb + 96,
+                                                               &racc[w][0][0], lane, tg, th,
+                                                               (int64_t)J * 64, n_major, ax, ay,
+                                                               az, ka);
+        } else if (PREC == 1 && fp32) {
+            tile_sweep32<KMT, KMT, false, Q0, Q1>(sb, sb + 32, sb + 64, sgf[SPLIT ? w : 0],
+                                                  &racc[w][0][0], lane, tg, tgf, ax, ay, az);
+        } else {
+            tile_sweep<KMT, KMT, false, Q0, Q1>(sb, sb + 32, sb + 64, sb + 96, &racc[w][0][0],
+                                                lane, tg, ax, ay, az,
+                                                PolyConst{vreg_const(1.875), vreg_const(1.5)});
+        }
     }
     NB_MUTUAL_MARK(2);
     if (PREC == 2) {
 #pragma unroll
-        for (int t = 0; t < KT; ++t) {
+        for (int t = 0; t < KMT; ++t) {
             ax[t] += (double)ka[t].s[0] - (double)ka[t].c[0];
             ay[t] += (double)ka[t].s[1] - (double)ka[t].c[1];
             az[t] += (double)ka[t].s[2] - (double)ka[t].c[2];
         }
     }
-    // the four waves' target sums, added in wave order
-    double (*comb)[KT][3][64] = reinterpret_cast<double (*)[KT][3][64]>(combp);
+    // the four waves' target sums, added in wave order (the buffer held the
+    // staged targets: every wave has read them before this barrier)
+    __syncthreads();
+    double (*comb)[KMT][3][64] = reinterpret_cast<double (*)[KMT][3][64]>(cbuf);
     if (w > 0) {
 #pragma unroll
-        for (int t = 0; t < KT; ++t) {
+        for (int t = 0; t < KMT; ++t) {
             comb[w - 1][t][0][lane] = ax[t];
             comb[w - 1][t][1][lane] = ay[t];
             comb[w - 1][t][2][lane] = az[t];
         }
     }
     __syncthreads();
+    const bool second = Q0 > 0;
     if (w == 0) {
         for (int o = 0; o < 3; ++o) {
 #pragma unroll
-            for (int t = 0; t < KT; ++t) {
+            for (int t = 0; t < KMT; ++t) {
                 ax[t] += comb[o][t][0][lane];
                 ay[t] += comb[o][t][1][lane];
                 az[t] += comb[o][t][2][lane];
             }
         }
+        const int tslot = second ? xslot + tl.D : r;
 #pragma unroll
-        for (int t = 0; t < KT; ++t) {
+        for (int t = 0; t < KMT; ++t) {
             const int64_t i = (int64_t)(I0 + t) * 64 + lane;
             if (i < n) {
-                double* pt = part + (int64_t)r * plane;
+                double* pt = part + (int64_t)tslot * plane;
                 __builtin_nontemporal_store(ax[t], &pt[i]);
                 __builtin_nontemporal_store(ay[t], &pt[n + i]);
                 __builtin_nontemporal_store(az[t], &pt[2 * n + i]);
@@ -658,7 +692,7 @@ __device__ __forceinline__ void mutual_half_body(const double* __restrict__ pos,
     }
     const int64_t j = (int64_t)J * 64 + lane;
     if (j < n) {
-        double* ps = part + (int64_t)(half == 0 ? g : xslot) * plane;
+        double* ps = part + (int64_t)(second ? xslot : g) * plane;
         __builtin_nontemporal_store(racc[w][0][lane], &ps[j]);
         __builtin_nontemporal_store(racc[w][1][lane], &ps[n + j]);
         __builtin_nontemporal_store(racc[w][2][lane], &ps[2 * n + j]);
@@ -690,10 +724,15 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
     double (*comb)[Shape::kSets][KMT][3][64] =
         reinterpret_cast<double (*)[Shape::kSets][KMT][3][64]>(cbuf);
     if constexpr (KMT == 4 && KMW == 4) {
-        static_assert(sizeof(cbuf) >= 3 * 2 * 3 * 64 * sizeof(double), "half-pair sums fit");
-        if (half >= 0) {
-            mutual_half_body<PREC>(pos, gm, n, n_major, g, r, half, xslot, part, src,
-                                    SPLIT ? sgf : nullptr, racc, cbuf);
+        static_assert(sizeof(cbuf) >= 3 * 4 * 3 * 64 * sizeof(double), "half-pair sums fit");
+        if (half == 0) {
+            mutual_half_body<PREC, 0, 2>(pos, gm, n, n_major, tl, g, r, xslot, part, src,
+                                         SPLIT ? sgf : nullptr, racc, cbuf);
+            return;
+        }
+        if (half == 1) {
+            mutual_half_body<PREC, 2, 4>(pos, gm, n, n_major, tl, g, r, xslot, part, src,
+                                         SPLIT ? sgf : nullptr, racc, cbuf);
             return;
         }
     }
@@ -849,13 +888,22 @@ __device__ __forceinline__ void mutual_unit(const double* __restrict__ pos,
                 __builtin_nontemporal_store(ax[t] + racc[jb][0][lane], &pt[i]);
                 __builtin_nontemporal_store(ay[t] + racc[jb][1][lane], &pt[stride + i]);
                 __builtin_nontemporal_store(az[t] + racc[jb][2][lane], &pt[2 * stride + i]);
-                // extra slot R + d - 1 is written by pair (g - d, g) if split
+                // extra slot R + d - 1 (reactions) is written by the split
+                // pair (g - d, g), R + D + d - 1 (targets) by the split pair
+                // (g, g + d); zeros where the pair is whole
                 for (int d = 1; d <= tl.D; ++d) {
-                    if (g >= d && (d < tl.D || g - d < tl.kD)) continue;
-                    double* pz = part + (int64_t)(tl.R + d - 1) * plane;
-                    __builtin_nontemporal_store(0.0, &pz[i]);
-                    __builtin_nontemporal_store(0.0, &pz[stride + i]);
-                    __builtin_nontemporal_store(0.0, &pz[2 * stride + i]);
+                    if (!mt_is_split(tl, g - d, d)) {
+                        double* pz = part + (int64_t)(tl.R + d - 1) * plane;
+                        __builtin_nontemporal_store(0.0, &pz[i]);
+                        __builtin_nontemporal_store(0.0, &pz[stride + i]);
+                        __builtin_nontemporal_store(0.0, &pz[2 * stride + i]);
+                    }
+                    if (!mt_is_split(tl, g, d)) {
+                        double* pz = part + (int64_t)(tl.R + tl.D + d - 1) * plane;
+                        __builtin_nontemporal_store(0.0, &pz[i]);
+                        __builtin_nontemporal_store(0.0, &pz[stride + i]);
+                        __builtin_nontemporal_store(0.0, &pz[2 * stride + i]);
+                    }
                 }
             }
         }
@@ -1212,7 +1260,7 @@ static MutualTail mutual_tail(int64_t n, int tpl, int waves)
 int mutual_slots(int64_t n, int tpl, int waves)
 {
     const MutualTail t = mutual_tail(n, tpl, waves);
-    return t.R + t.D;
+    return t.R + 2 * t.D;
 }
 
 bool mutual_shape_supported(int tpl, int waves)

@@ -49,7 +49,7 @@ extern "C" __attribute__((visibility("default"))) int clock_probe_force(const do
     const MutualTail tl = mutual_tail(n, 4, 4);
     const int64_t pairs = (int64_t)tl.R * (tl.R + 1) / 2;
     const int grid = (int)(tl.F + 2 * (pairs - tl.F));
-    const int slots = tl.R + tl.D;
+    const int slots = mutual_slots(n, 4, 4);
     double *pos = nullptr, *gm = nullptr, *part = nullptr;
     unsigned long long* clk = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -1,7 +1,8 @@
 // Host-side check of the each-pair-once pass's workgroup decode (built from
 // the kernel source itself, run on the CPU): for every size, every range pair
-// runs once, whole or as both halves, and every body receives each of its
-// partial slots exactly once, with every slot inside the workspace.
+// runs once, whole or as both halves (sub-phases 0-1 and 2-3, each over all
+// its targets and sources), and every body receives each of its partial
+// slots exactly once, with every slot inside the workspace.
 #include "kernels_mutual.hip"
 #include <cstdio>
 #include <vector>
@@ -10,6 +11,7 @@ static int check(int64_t n, int tpl, int waves, bool verbose)
 {
     const MutualTail tl = mutual_tail(n, tpl, waves);
     const int R = tl.R, S = mutual_slots(n, tpl, waves), nb = (int)((n + 63) / 64);
+    if (S != R + 2 * tl.D) { printf("n=%ld slots %d R=%d D=%d\n", (long)n, S, R, tl.D); return 1; }
     const int64_t U = (int64_t)R * (R + 1) / 2;
     const int64_t grid = tl.F + 2 * (U - tl.F);
     std::vector<int> whole((size_t)R * R, 0), halves((size_t)R * R * 2, 0);
@@ -28,16 +30,16 @@ static int check(int64_t n, int tpl, int waves, bool verbose)
                 for (int t = 0; t < 4; ++t) for (int l = 0; l < 64; ++l) {
                     const int64_t i = (int64_t)(4 * g + t) * 64 + l;
                     mark(i, g);
-                    for (int d = 1; d <= tl.D; ++d) {
-                        if (g >= d && (d < tl.D || g - d < tl.kD)) continue;
-                        mark(i, tl.R + d - 1);
+                    for (int d = 1; d <= tl.D; ++d) {   // the diagonal workgroup's zeros
+                        if (!mt_is_split(tl, g - d, d)) mark(i, tl.R + d - 1);
+                        if (!mt_is_split(tl, g, d)) mark(i, tl.R + tl.D + d - 1);
                     }
                 }
             }
         } else {
             if (r <= g) { printf("n=%ld split diagonal pair\n", (long)n); return 1; }
             halves[((size_t)g * R + r) * 2 + half]++;
-            for (int t = 0; t < 2; ++t) for (int l = 0; l < 64; ++l) mark((int64_t)(4 * g + 2 * half + t) * 64 + l, r);
+            for (int t = 0; t < 4; ++t) for (int l = 0; l < 64; ++l) mark((int64_t)(4 * g + t) * 64 + l, half == 0 ? r : xs + tl.D);
             for (int jb = 0; jb < 4; ++jb) for (int l = 0; l < 64; ++l) mark((int64_t)(4 * r + jb) * 64 + l, half == 0 ? g : xs);
             if (half == 1 && (xs < R || xs >= S)) { printf("n=%ld xslot %d\n", (long)n, xs); return 1; }
         }

@@ -60,7 +60,7 @@ extern "C" __attribute__((visibility("default"))) int timeline_probe_force(
     const int64_t grid = tl.F + 2 * (pairs - tl.F);
     *grid_out = (int)grid;
     if (grid * 32 > out_len) return 1;
-    const int slots = tl.R + tl.D;
+    const int slots = mutual_slots(n, 4, 4);
     double *pos = nullptr, *gm = nullptr, *part = nullptr;
     unsigned long long* rec = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -3,9 +3,10 @@
 tests/host/mutual_schedule.hip includes the kernel source and runs its
 host-and-device decode on the host for 2,500 sizes and two shapes: every
 range pair (g, r), r >= g, runs once, whole or as both halves of a split
-pair, and every body receives each of its partial slots exactly once (the
-halves' targets, the reactions of both halves, the diagonal workgroup's
-zero-filled extra slots).  Nothing runs on a GPU."""
+pair (sub-phases 0-1 and 2-3, each over all its targets and sources), and
+every body receives each of its partial slots exactly once (both halves'
+targets and reactions, the diagonal workgroup's zero-filled extra slots).
+Nothing runs on a GPU."""
 import os
 import shutil
 import subprocess
@@ -38,4 +39,4 @@ def test_mutual_decode_covers_every_pair_and_slot_once(tmp_path):
     print(run.stdout[-3000:])
     assert run.returncode == 0 and "ok (" in run.stdout, run.stdout[-2000:]
     # the headline size: 768 whole pairs, 93 split over three super-diagonals
-    assert "n=10425 tile(4,4) R=41 pairs=861 F=768 D=3 kD=14 grid=954 slots=44" in run.stdout
+    assert "n=10425 tile(4,4) R=41 pairs=861 F=768 D=3 kD=14 grid=954 slots=47" in run.stdout
