@@ -356,10 +356,10 @@ def test_mutual_pairs_split_workloads(k, tile):
 @pytest.mark.parametrize("n", [8192, 9990, 10240, 13056, 30000, 45500])
 def test_mutual_pairs_split_last_round(n):
     """Each pair once, shape (4, 4), at sizes whose last round of range pairs
-    is split into halves (one to three super-diagonals of split pairs, their
-    reactions in extra slots, the unused extra slots zero-filled by the
-    diagonal workgroups): FP64 and split accelerations against the oracle,
-    and 30 steps bitwise equal to 15 + 15."""
+    is split into halves by sub-phases (one to three super-diagonals of split
+    pairs, the second halves' target sums and reactions in extra slots, the
+    unused extra slots zero-filled by the diagonal workgroups): FP64 and split
+    accelerations against the oracle, and 30 steps bitwise equal to 15 + 15."""
     s = S.solar_system(41 + n, n - 31, n_major=30)
     ref = oracle.accel(s.pos, s.mass, s.G)
     m = T(s.mass)
