@@ -339,7 +339,7 @@ int64_t vjp_chunk_length(int64_t n, const Tile& t)
 
 int vjp_chunks(int64_t n, const Tile& t)
 {
-    if (t.variant == 5) return mutual_ranges(n);   // each pair once: one slot per range
+    if (t.variant == 5) return mutual_slots(n, t.tpl, t.waves);   // each pair once
     const int64_t L = vjp_chunk_length(n, t);
     return (int)((n + L - 1) / L);
 }

@@ -947,12 +947,14 @@ __global__ __launch_bounds__(64 * KMW) void k_force_mutual_batched(
 //   body j gains -G K(d) w       (K is even in d, w odd in the pair),
 // and in the mass gradient q gains -G u_j.d/|d|^3, j gains +G u_q.d/|d|^3.
 // The pass runs on lam (u = c lam) and scales by G c at the store, as the
-// one-way pass does.  Schedule as the force pass above, whole range pairs
-// only: the four reaction sums (three position components, the mass term)
-// travel along the row with their source.  Partial slot c of plane k (0..2:
-// position gradient, 3: mass gradient) of body i at part[(4c + k) n + i];
-// slot r holds workgroup (g, r)'s target sums, slot g its reactions, so a
-// body receives exactly one partial per range.
+// one-way pass does.  Schedule as the force pass above, the last round's
+// pairs of shape (4, 4) split into sub-phase halves the same way: the four
+// reaction sums (three position components, the mass term) travel along the
+// row with their source.  Partial slot c of plane k (0..2: position gradient,
+// 3: mass gradient) of body i at part[(4c + k) n + i]; slot r holds workgroup
+// (g, r)'s target sums, slot g its reactions, a second half's go to the
+// extra slots of its pair, so a body receives each of its R + 2D slots
+// exactly once.
 
 struct VBody {
     double x, y, z, m, ux, uy, uz;
@@ -1001,15 +1003,16 @@ struct VAcc {
 
 // One tile (KMT target blocks of a wave against source block jb), the
 // geometry of tile_sweep: targets t < NSYM both ways, t == NSYM one way when
-// DIAG (the diagonal block, its own body skipped), t > NSYM not at all.
-template <int KMT, int NSYM, bool DIAG>
+// DIAG (the diagonal block, its own body skipped), t > NSYM not at all;
+// sub-phases Q0 .. Q1 - 1.
+template <int KMT, int NSYM, bool DIAG, int Q0 = 0, int Q1 = 4>
 __device__ __forceinline__ void vjp_tile(const VSrc& S, int jb, double* __restrict__ ra, int lane,
                                          const VBody (&tg)[KMT], VAcc (&o)[KMT])
 {
     constexpr bool kReact = NSYM > 0;
     const int row = lane >> 4;
     const int col = lane & 15;
-    for (int q = 0; q < 4; ++q) {
+    for (int q = Q0; q < Q1; ++q) {
         const int grp = (row + q) & 3;
         const int home = 16 * grp + col;
         double rx = 0.0, ry = 0.0, rz = 0.0, rg = 0.0;
@@ -1088,7 +1091,7 @@ template <int KMT, int KMW>
 __global__ __launch_bounds__(64 * KMW) void k_vjp_mutual(const double* __restrict__ pos,
                                                          const double* __restrict__ mass,
                                                          const double* __restrict__ lam,
-                                                         double gc, int64_t n, int R,
+                                                         double gc, int64_t n, MutualTail tl,
                                                          double* __restrict__ part)
 {
     using Shape = MutualShape<KMT, KMW>;
@@ -1101,9 +1104,11 @@ __global__ __launch_bounds__(64 * KMW) void k_vjp_mutual(const double* __restric
     VSrc& S = *reinterpret_cast<VSrc*>(smem);
     Comb& comb = *reinterpret_cast<Comb*>(smem);
 
-    const MutualTail whole{R, (int)((int64_t)R * (R + 1) / 2), 0, 0};
+    // shape (4, 4): the pairs past the last whole round run as halves by
+    // sub-phases, as in the force pass (the second half's target sums and
+    // reactions in the extra slots R + D + d - 1 and R + d - 1)
     int g, r, half, xslot;
-    mt_decode(whole, blockIdx.x, g, r, half, xslot);
+    mt_decode(tl, blockIdx.x, g, r, half, xslot);
 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -1155,7 +1160,18 @@ __global__ __launch_bounds__(64 * KMW) void k_vjp_mutual(const double* __restric
     for (int p = 0; p < Shape::kPhases; ++p) {
         const int jb = (w + p) % kMM;
         const int J = J0 + jb;
-        if (J < nb && J >= I0) vjp_tile_dispatch<KMT>(J - I0, S, jb, &racc[jb][0][0], lane, tg, o);
+        if (J < nb && J >= I0) {
+            if constexpr (KMT == 4 && KMW == 4) {   // a half: r > g, so J - I0 >= 4
+                if (half == 0)
+                    vjp_tile<4, 4, false, 0, 2>(S, jb, &racc[jb][0][0], lane, tg, o);
+                else if (half == 1)
+                    vjp_tile<4, 4, false, 2, 4>(S, jb, &racc[jb][0][0], lane, tg, o);
+                else
+                    vjp_tile_dispatch<KMT>(J - I0, S, jb, &racc[jb][0][0], lane, tg, o);
+            } else {
+                vjp_tile_dispatch<KMT>(J - I0, S, jb, &racc[jb][0][0], lane, tg, o);
+            }
+        }
         __syncthreads();
     }
 
@@ -1184,12 +1200,14 @@ __global__ __launch_bounds__(64 * KMW) void k_vjp_mutual(const double* __restric
     }
 
     if (r > g) {   // targets' sums to slot r, the sources' reactions to slot g
+        const int tslot = half == 1 ? xslot + tl.D : r;
+        const int rslot = half == 1 ? xslot : g;
         if (h == 0) {
 #pragma unroll
             for (int t = 0; t < KMT; ++t) {
                 const int64_t i = (int64_t)(I0 + t) * 64 + lane;
                 if (i < n) {
-                    double* pt = part + (int64_t)r * plane;
+                    double* pt = part + (int64_t)tslot * plane;
                     __builtin_nontemporal_store(gc * o[t].x, &pt[i]);
                     __builtin_nontemporal_store(gc * o[t].y, &pt[n + i]);
                     __builtin_nontemporal_store(gc * o[t].z, &pt[2 * n + i]);
@@ -1200,7 +1218,7 @@ __global__ __launch_bounds__(64 * KMW) void k_vjp_mutual(const double* __restric
         for (int jb = w; jb < kMM; jb += KMW) {
             const int64_t j = (int64_t)(J0 + jb) * 64 + lane;
             if (j < n) {
-                double* ps = part + (int64_t)g * plane;
+                double* ps = part + (int64_t)rslot * plane;
                 __builtin_nontemporal_store(gc * racc[jb][0][lane], &ps[j]);
                 __builtin_nontemporal_store(gc * racc[jb][1][lane], &ps[n + j]);
                 __builtin_nontemporal_store(gc * racc[jb][2][lane], &ps[2 * n + j]);
@@ -1218,6 +1236,18 @@ __global__ __launch_bounds__(64 * KMW) void k_vjp_mutual(const double* __restric
                 __builtin_nontemporal_store(gc * (o[t].y + racc[jb][1][lane]), &pt[n + i]);
                 __builtin_nontemporal_store(gc * (o[t].z + racc[jb][2][lane]), &pt[2 * n + i]);
                 __builtin_nontemporal_store(-gc * (o[t].g + racc[jb][3][lane]), &pt[3 * n + i]);
+                // zeros in the extra slots of the pairs (g - d, g), (g, g + d)
+                // that are not split
+                for (int d = 1; d <= tl.D; ++d) {
+                    for (int e = 0; e < 2; ++e) {
+                        if (mt_is_split(tl, e == 0 ? g - d : g, d)) continue;
+                        double* pz = part + (int64_t)(tl.R + (e == 0 ? 0 : tl.D) + d - 1) * plane;
+                        __builtin_nontemporal_store(0.0, &pz[i]);
+                        __builtin_nontemporal_store(0.0, &pz[n + i]);
+                        __builtin_nontemporal_store(0.0, &pz[2 * n + i]);
+                        __builtin_nontemporal_store(0.0, &pz[3 * n + i]);
+                    }
+                }
             }
         }
     }
@@ -1353,18 +1383,19 @@ hipError_t launch_vjp_mutual(int tpl, int waves, const double* pos, const double
 {
     if (n < 1 || n > kMutualMaxN || !mutual_shape_supported(tpl, waves))
         return hipErrorInvalidValue;
-    const int R = mutual_ranges(n);
-    const dim3 grid((unsigned)((int64_t)R * (R + 1) / 2));
+    const MutualTail tl = mutual_tail(n, tpl, waves);
+    const int64_t U = (int64_t)tl.R * (tl.R + 1) / 2;
+    const dim3 grid((unsigned)(tl.F + 2 * (U - tl.F)));
     const dim3 block((unsigned)(64 * waves));
     const double gc = G * cu;
     if (tpl == 1)
-        hipLaunchKernelGGL((k_vjp_mutual<1, 4>), grid, block, 0, s, pos, mass, lam, gc, n, R, part);
+        hipLaunchKernelGGL((k_vjp_mutual<1, 4>), grid, block, 0, s, pos, mass, lam, gc, n, tl, part);
     else if (tpl == 2 && waves == 2)
-        hipLaunchKernelGGL((k_vjp_mutual<2, 2>), grid, block, 0, s, pos, mass, lam, gc, n, R, part);
+        hipLaunchKernelGGL((k_vjp_mutual<2, 2>), grid, block, 0, s, pos, mass, lam, gc, n, tl, part);
     else if (tpl == 2)
-        hipLaunchKernelGGL((k_vjp_mutual<2, 4>), grid, block, 0, s, pos, mass, lam, gc, n, R, part);
+        hipLaunchKernelGGL((k_vjp_mutual<2, 4>), grid, block, 0, s, pos, mass, lam, gc, n, tl, part);
     else
-        hipLaunchKernelGGL((k_vjp_mutual<4, 4>), grid, block, 0, s, pos, mass, lam, gc, n, R, part);
+        hipLaunchKernelGGL((k_vjp_mutual<4, 4>), grid, block, 0, s, pos, mass, lam, gc, n, tl, part);
     return hipGetLastError();
 }
 

@@ -1,8 +1,9 @@
-// Host-side check of the each-pair-once pass's workgroup decode (built from
+// Host-side check of the each-pair-once passes' workgroup decode (built from
 // the kernel source itself, run on the CPU): for every size, every range pair
 // runs once, whole or as both halves (sub-phases 0-1 and 2-3, each over all
 // its targets and sources), and every body receives each of its partial
-// slots exactly once, with every slot inside the workspace.
+// slots exactly once, with every slot inside the workspace.  The force pass
+// and the transpose-Jacobian pass share this decode and these slot rules.
 #include "kernels_mutual.hip"
 #include <cstdio>
 #include <vector>

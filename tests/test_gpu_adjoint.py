@@ -136,6 +136,28 @@ def test_adjoint_each_pair_once_at_10425_bodies():
     nb.reset_caches()
 
 
+@pytest.mark.parametrize("n", [8192, 9990, 13056])
+def test_adjoint_each_pair_once_split_last_round(n):
+    """The pair-once transpose-Jacobian pass, shape (4, 4), at sizes whose
+    last round of range pairs runs as halves by sub-phases (the second
+    halves' sums and reactions in extra slots, the unused ones zero-filled):
+    two steps against the oracle's reverse sweep, and a repeat bitwise."""
+    nb.reset_caches()
+    s = S.solar_system(45 + n, n - 31, n_major=30)
+    nb.set_tile(1, "fp64", s.n, 4, 4, 1, 5)
+    rng = np.random.default_rng(n)
+    lr, lv = rng.normal(size=(3, s.n)) * 1e-8, rng.normal(size=(3, s.n)) * 1e-6
+    gr, gv, gm = oracle.adjoint(s.pos, s.vel, s.mass, s.G, 0.1, 2, lr, lv)
+    args = (T(s.pos), T(s.vel), T(s.mass), s.G, 0.1, 2, 1, T(lr), T(lv))
+    Gr, Gv, Gm, _, _ = nb.verlet_adjoint(*args)
+    er, ev, em = nrel(H(Gr), gr), nrel(H(Gv), gv), nrel(H(Gm), gm)
+    print(f"n={s.n} split last round: rel err r0 {er:.2e} v0 {ev:.2e} m {em:.2e}", flush=True)
+    assert er <= 1e-10 and ev <= 1e-10 and em <= 1e-10
+    again = nb.verlet_adjoint(*args)
+    assert all(torch.equal(a, b) for a, b in zip(again[:3], (Gr, Gv, Gm)))
+    nb.reset_caches()
+
+
 def test_adjoint_autotune_then_parity():
     """The autotuner over the transpose-Jacobian pass's tiles (LDS-staged and
     scalar-operand sources) keeps a supported tile for the size class, and the
