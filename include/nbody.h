@@ -278,8 +278,8 @@ int32_t nbody_get_flags(void* workspace, void* stream, int32_t clear, int32_t* f
  * whole round of 256 workgroups are few (at most 128, of at most 16,384
  * pairs), each of them runs as two half-size workgroups and a few extra
  * slots take the second halves' reactions (44 slots at n = 10,425).  Results
- * stay bitwise repeatable.  The heuristic picks (4, 4) from n = 4,300 (FP64)
- * or 8,500 (split) up to n = 131,072. */
+ * stay bitwise repeatable.  The heuristic picks (4, 4) from n = 4,096 (FP64)
+ * or 8,000 (split) up to n = 131,072. */
 typedef struct {
     int32_t targets_per_lane;
     int32_t waves;

@@ -88,14 +88,18 @@ constexpr int64_t kFusedMax = 16384;
 // From these sizes single systems default to the each-pair-once pass
 // (variant 5, four waves sharing four target blocks per lane), up to
 // kMutualMaxN bodies; below them the pass has too few workgroups to fill the
-// chip.  The split form's one-way
-// pass is cheaper than the FP64 one, so its crossover comes later.
-constexpr int64_t kMutualDefault = 4300;
-constexpr int64_t kMutualSplitDefault = 8500;
+// chip.  The FP64 one-way pass takes two waves per 64 targets from 4,096
+// bodies, where the pair-once step is already the faster (21.1 against
+// 24.6 us per step at 4,300; 20.9 against 20.0 at 4,000 with one wave); the
+// split form's one-way pass is cheaper than the FP64 one, so its crossover
+// comes later (35.1 against 37.4 us per step at 8,000, 31.1 against 30.3
+// at 7,000).
+constexpr int64_t kMutualDefault = 4096;
+constexpr int64_t kMutualSplitDefault = 8000;
 // The adjoint's transpose-Jacobian pass with each pair once, from this size
-// (shape (kVjpMutualTpl, 4); measured: 76.2 against 89.1 us for the one-way
-// pass at 8,000 bodies, 52.7 against 49.2 at 6,000).
-constexpr int64_t kVjpMutualDefault = 7000;
+// (shape (kVjpMutualTpl, 4); measured: 29.9 against 36.5 us for the one-way
+// pass at 5,000 bodies, 29.7 against 28.4 at 4,300).
+constexpr int64_t kVjpMutualDefault = 4500;
 constexpr int kVjpMutualTpl = 4;
 
 // The each-pair-once pass serves single systems (FP64 or split) of up to
@@ -121,7 +125,7 @@ int part_slots(int64_t n)
 // 1024 lanes allow, at most 16); then one kernel per step with 8 waves
 // sharing each 64 targets; otherwise about 8192 wavefronts in flight;
 // scalar-operand sources for FP64 below ~3e4 bodies (each pair once from
-// 4,300, split from 8,500, to 131,072), LDS tiles with 4 targets per lane
+// 4,096, split from 8,000, to 131,072), LDS tiles with 4 targets per lane
 // above; the split form's one-way passes prefer the LDS tiles at every size.
 // The force pass alone (variants 0-2): partials for a separate epilogue.
 Tile force_only_tile(int prec, int64_t n)

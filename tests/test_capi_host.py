@@ -146,10 +146,10 @@ def test_tile_table():
     lib = _lib()
     lib.nbody_reset_caches()
     t = C.Tile()
-    # defaults: each pair once (variant 5) up to 131,072 bodies, from 4,300
-    # (FP64) or 8,500 (split), one-way passes on either side
-    for prec, n, variant in [(0, 4299, 1), (0, 4300, 5), (0, 10425, 5), (0, 40000, 5),
-                             (0, 131072, 5), (0, 131073, 0), (1, 8499, 0), (1, 8500, 5),
+    # defaults: each pair once (variant 5) up to 131,072 bodies, from 4,096
+    # (FP64) or 8,000 (split), one-way passes on either side
+    for prec, n, variant in [(0, 4095, 1), (0, 4096, 5), (0, 10425, 5), (0, 40000, 5),
+                             (0, 131072, 5), (0, 131073, 0), (1, 7999, 0), (1, 8000, 5),
                              (1, 10425, 5), (1, 131072, 5), (1, 131073, 0)]:
         assert lib.nbody_get_tile(0, prec, n, ctypes.byref(t)) == C.NBODY_OK
         assert t.variant == variant, (prec, n, t.variant)
@@ -164,10 +164,10 @@ def test_tile_table():
     assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == (1, 2, 9, 1)
     assert lib.nbody_set_tile(0, 0, 10425, ctypes.byref(C.Tile(1, 2, 9, 3))) == C.NBODY_EINVAL
     # the adjoint pass defaults to scalar operands, 2 waves, up to 64 source
-    # chunks of >= 16 bodies, within the workspace's chunk cap; from 7,000 to
+    # chunks of >= 16 bodies, within the workspace's chunk cap; from 4,500 to
     # 131,072 bodies to each pair once in the (4, 4) shape
     for n, want in ((20, (1, 2, 1, 1)), (100, (1, 2, 6, 1)), (2079, (1, 2, 64, 1)),
-                    (6999, (1, 2, 64, 1)), (7000, (4, 4, 1, 5)), (131072, (4, 4, 1, 5)),
+                    (4499, (1, 2, 64, 1)), (4500, (4, 4, 1, 5)), (131072, (4, 4, 1, 5)),
                     (131073, (1, 2, 31, 1))):
         assert lib.nbody_get_tile(1, 0, n, ctypes.byref(t)) == C.NBODY_OK
         assert (t.targets_per_lane, t.waves, t.chunks, t.variant) == want, n
