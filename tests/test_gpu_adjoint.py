@@ -158,6 +158,26 @@ def test_adjoint_each_pair_once_split_last_round(n):
     nb.reset_caches()
 
 
+@pytest.mark.parametrize("n,variant", [(4499, 1), (4500, 5)])
+def test_adjoint_default_tile_at_the_pair_once_boundary(n, variant):
+    """The transpose-Jacobian pass's default tile on either side of the size
+    where it switches to each pair once: two steps against the oracle's
+    reverse sweep."""
+    nb.reset_caches()
+    s = S.solar_system(48 + n, n - 31, n_major=30)
+    assert nb.get_tile(1, "fp64", s.n)["variant"] == variant
+    rng = np.random.default_rng(n)
+    lr, lv = rng.normal(size=(3, s.n)) * 1e-8, rng.normal(size=(3, s.n)) * 1e-6
+    gr, gv, gm = oracle.adjoint(s.pos, s.vel, s.mass, s.G, 0.1, 2, lr, lv)
+    Gr, Gv, Gm, _, _ = nb.verlet_adjoint(T(s.pos), T(s.vel), T(s.mass), s.G, 0.1, 2, 1,
+                                         T(lr), T(lv))
+    er, ev, em = nrel(H(Gr), gr), nrel(H(Gv), gv), nrel(H(Gm), gm)
+    print(f"n={s.n} default variant {variant}: rel err r0 {er:.2e} v0 {ev:.2e} m {em:.2e}",
+          flush=True)
+    assert er <= 1e-10 and ev <= 1e-10 and em <= 1e-10
+    nb.reset_caches()
+
+
 def test_adjoint_autotune_then_parity():
     """The autotuner over the transpose-Jacobian pass's tiles (LDS-staged and
     scalar-operand sources) keeps a supported tile for the size class, and the

@@ -353,6 +353,28 @@ def test_mutual_pairs_split_workloads(k, tile):
     assert np.array_equal(H(outs[0][0]), H(outs[1][0])) and np.array_equal(H(outs[0][1]), H(outs[1][1]))
 
 
+@pytest.mark.parametrize("precision,n,variant", [("fp64", 4095, 1), ("fp64", 4096, 5),
+                                                   ("split", 7999, 0), ("split", 8000, 5)])
+def test_default_tiles_at_the_pair_once_boundaries(precision, n, variant):
+    """The default tiles on either side of the sizes where the pass switches
+    between one-way and each-pair-once: the expected variant, accelerations
+    against the oracle, and a 20-step run equal to 10 + 10."""
+    nb.reset_caches()
+    s = S.solar_system(47 + n, n - 31, n_major=30)
+    assert nb.get_tile(0, precision, n)["variant"] == variant
+    m = T(s.mass)
+    tol = 1e-13 if precision == "fp64" else 2e-12
+    e = rel(H(nb.accel(T(s.pos), m, s.G, precision=precision)), oracle.accel(s.pos, s.mass, s.G))
+    log(f"default tile {precision} n={n} variant {variant}: rel {e:.2e}")
+    assert e <= tol
+    p1, v1 = T(s.pos), T(s.vel)
+    nb.verlet_run(p1, v1, m, s.G, 0.1, 20, precision=precision)
+    p2, v2 = T(s.pos), T(s.vel)
+    nb.verlet_run(p2, v2, m, s.G, 0.1, 10, precision=precision)
+    nb.verlet_run(p2, v2, m, s.G, 0.1, 10, precision=precision)
+    assert np.array_equal(H(p1), H(p2)) and np.array_equal(H(v1), H(v2))
+
+
 @pytest.mark.parametrize("n", [8192, 9990, 10240, 13056, 30000, 45500])
 def test_mutual_pairs_split_last_round(n):
     """Each pair once, shape (4, 4), at sizes whose last round of range pairs
