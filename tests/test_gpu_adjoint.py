@@ -136,6 +136,29 @@ def test_adjoint_each_pair_once_at_10425_bodies():
     nb.reset_caches()
 
 
+def test_adjoint_pipelined_segments_with_split_last_round_bitwise():
+    """The pipelined reverse sweep at 8,192 bodies, where the default
+    transpose-Jacobian pass is each pair once with its last round of range
+    pairs run as sub-phase halves: 24 steps in one segment (K = 24) and in
+    five pipelined ones (K = 5, the last ragged) give identical gradients,
+    and those match the oracle's reverse sweep."""
+    nb.reset_caches()
+    s = S.solar_system(49, 8192 - 31, n_major=30)
+    assert nb.get_tile(1, "fp64", s.n)["variant"] == 5
+    rng = np.random.default_rng(24)
+    lr, lv = rng.normal(size=(3, s.n)) * 1e-8, rng.normal(size=(3, s.n)) * 1e-6
+    r, v, m = T(s.pos), T(s.vel), T(s.mass)
+    outs = [[H(x) for x in nb.verlet_adjoint(r, v, m, s.G, 0.1, 24, K, T(lr), T(lv))[:3]]
+            for K in (24, 5)]
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    gr, gv, gm = oracle.adjoint(s.pos, s.vel, s.mass, s.G, 0.1, 24, lr, lv)
+    er, ev, em = nrel(outs[0][0], gr), nrel(outs[0][1], gv), nrel(outs[0][2], gm)
+    print(f"n={s.n} 24 steps pipelined: rel err r0 {er:.2e} v0 {ev:.2e} m {em:.2e}", flush=True)
+    assert er <= 1e-10 and ev <= 1e-10 and em <= 1e-10
+    nb.reset_caches()
+
+
 @pytest.mark.parametrize("n", [8192, 9990, 13056])
 def test_adjoint_each_pair_once_split_last_round(n):
     """The pair-once transpose-Jacobian pass, shape (4, 4), at sizes whose
