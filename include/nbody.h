@@ -254,8 +254,8 @@ int32_t nbody_get_flags(void* workspace, void* stream, int32_t clear, int32_t* f
  * workgroup (1, 2, 4, 8), source chunks (1..64) and how sources reach the
  * lanes (variant 0: staged through LDS; 1: read once per wavefront into
  * scalar registers; 2: as 1, the waves of a workgroup sharing targets and
- * splitting the sources; the adjoint pass supports variants 0 and 1 and
- * defaults to 1).
+ * splitting the sources; the adjoint pass supports variants 0, 1 and 5
+ * and defaults to 1 below 4,500 bodies, to 5 in shape (4, 4) from there).
  * Variant 3 (kind 0 only, n <= 512, targets_per_lane = 1, waves = 16):
  * one workgroup holds the system in LDS and runs whole steps, force pass,
  * reduction and kick-drift-kick, in one launch; chunks is then the number
@@ -265,7 +265,7 @@ int32_t nbody_get_flags(void* workspace, void* stream, int32_t clear, int32_t* f
  * 1): the waves of a workgroup split all sources of its targets, and the
  * same kernel applies the step's kicks and drift, so a step is one launch.
  * The heuristic picks it for 160 < n <= 512.
- * Variant 5 (kind 0; (targets_per_lane, waves) = (1, 4), (2, 2), (2, 4) or
+ * Variant 5 (kinds 0 and 1; (targets_per_lane, waves) = (1, 4), (2, 2), (2, 4) or
  * (4, 4); chunks 1): each unordered pair is evaluated once and the reaction
  * is added to the source (Newton's third law applied to Eq. (1)); in the
  * split form pairs of light bodies are evaluated in FP32 both ways and every
@@ -276,10 +276,12 @@ int32_t nbody_get_flags(void* workspace, void* stream, int32_t clear, int32_t* f
  * for a split last round (below), up to that size:
  * 1.6 GB at n = 131,072).  With (4, 4), when the range pairs past the last
  * whole round of 256 workgroups are few (at most 128, of at most 16,384
- * pairs), each of them runs as two half-size workgroups and a few extra
- * slots take the second halves' reactions (44 slots at n = 10,425).  Results
- * stay bitwise repeatable.  The heuristic picks (4, 4) from n = 4,096 (FP64)
- * or 8,000 (split) up to n = 131,072. */
+ * pairs), each of them runs as two workgroups over half of the sub-phases
+ * each, and extra slots take the second halves' target sums and reactions
+ * (47 slots at n = 10,425); the transpose-Jacobian pass (kind 1, variant 5,
+ * shape (4, 4)) splits its last round the same way.  Results stay bitwise
+ * repeatable.  The heuristic picks (4, 4) from n = 4,096 (FP64) or 8,000
+ * (split) up to n = 131,072, and for kind 1 from n = 4,500. */
 typedef struct {
     int32_t targets_per_lane;
     int32_t waves;
