@@ -54,6 +54,12 @@ def test_workspace_sizes():
     # for the each-pair-once pass (512 slots at 131,072), beyond that 2^22 / n
     assert ws(C.OP_RUN, 131072, 1, 5, 1, C.NBODY_FP64) >= 512 * 3 * 131072 * 8
     assert ws(C.OP_RUN, 131073, 1, 5, 1, C.NBODY_FP64) < 64 * 3 * 131073 * 8
+    # the pair-once passes at 10,425 bodies: 41 ranges and, with the last
+    # round split into halves, 2 x 3 extra slots (47); the force pass writes
+    # three planes per slot, the transpose-Jacobian pass four
+    assert ws(C.OP_RUN, 10425, 1, 5, 1, C.NBODY_FP64) >= 47 * 3 * 10425 * 8
+    assert ws(C.OP_ADJOINT, 10425, 1, 10, 5, C.NBODY_FP64) >= 47 * 4 * 10425 * 8
+    assert ws(C.OP_ADJOINT_SWEEP, 10425, 1, 10, 5, C.NBODY_FP64) >= 47 * 4 * 10425 * 8
     # RK4: the run's buffers plus stage velocity and two slope sums
     assert ws(C.OP_RK4, 10425, 1, 5, 1, C.NBODY_FP64) >= ws(C.OP_RUN, 10425, 1, 5, 1, C.NBODY_FP64) \
         + 3 * 3 * 10425 * 8
