@@ -1096,7 +1096,8 @@ __global__ __launch_bounds__(64 * KMW) void k_vjp_mutual(const double* __restric
 {
     using Shape = MutualShape<KMT, KMW>;
     // the waves' partial sums reuse the staged sources' space once the sweep
-    // is done (36 KB of LDS in all: four workgroups per CU)
+    // is done (36 KB of LDS in all, four workgroups per CU; shape (4, 4)
+    // stages its targets as well: 50 KB, three per CU)
     using Comb = double[Shape::kShare > 1 ? Shape::kShare - 1 : 1][Shape::kSets][KMT][4][64];
     static_assert(sizeof(Comb) <= sizeof(VSrc), "the sums fit in the sources' space");
     __shared__ double smem[sizeof(VSrc) / sizeof(double)];
