@@ -561,6 +561,19 @@ __host__ __device__ inline bool mt_is_split(const MutualTail& tl, int g, int d)
     return g >= 0 && g + d <= tl.R - 1 && (d < tl.D || g < tl.kD);
 }
 
+// The decode above listed by the host for passes of at most kMapMax
+// workgroups over at most 64 ranges, and handed over in the kernel's
+// arguments: a workgroup then reads its entry with one load, where the
+// closed form's scalar arithmetic (about 350 instructions) would delay its
+// first staging loads (0.6 us of a 46 us pass at 10,425 bodies, measured).
+// Entry b: g | r << 6 | (half + 1) << 12; a half's extra slot is R + r - g - 1.
+// count 0: the kernel runs the closed form.
+constexpr int kMapMax = 1536;
+struct MutualMap {
+    int32_t count;
+    uint16_t e[kMapMax];
+};
+
 // Half `half` of the split pair (g, r), r > g, by sub-phases: the four
 // target blocks of range g (four per lane) against source block 4r + w in
 // wave w, over sub-phases Q0 .. Q1 - 1 (half 0: 0 and 1, half 1: 2 and 3),
@@ -915,11 +928,19 @@ __global__ __launch_bounds__(64 * KMW) void k_force_mutual(const double* __restr
                                                            const double* __restrict__ gm,
                                                            int64_t n,
                                                            const int64_t* __restrict__ nmaj,
-                                                           MutualTail tl,
+                                                           MutualTail tl, MutualMap map,
                                                            double* __restrict__ part)
 {
     int g, r, half, xslot;
-    mt_decode(tl, blockIdx.x, g, r, half, xslot);
+    if (map.count > 0) {
+        const uint32_t v = __builtin_amdgcn_readfirstlane((uint32_t)map.e[blockIdx.x]);
+        g = (int)(v & 63u);
+        r = (int)((v >> 6) & 63u);
+        half = (int)(v >> 12) - 1;
+        xslot = half >= 0 ? tl.R + (r - g) - 1 : 0;
+    } else {
+        mt_decode(tl, blockIdx.x, g, r, half, xslot);
+    }
     mutual_unit<KMT, KMW, PREC>(pos, gm, n, n, PREC != 0 ? nmaj[0] : 0, g, r, part, tl, half,
                                 xslot);
 }
@@ -1300,24 +1321,45 @@ bool mutual_shape_supported(int tpl, int waves)
            (tpl == 4 && waves == 4);
 }
 
+// The kernel-argument list of a pass's decode (count 0 where it does not
+// fit), kept per host thread for the last shape of the split.
+static const MutualMap& mutual_map(const MutualTail& tl, int64_t grid)
+{
+    thread_local MutualTail last{-1, -1, -1, -1};
+    thread_local MutualMap m{};
+    if (last.R == tl.R && last.F == tl.F && last.D == tl.D && last.kD == tl.kD) return m;
+    m.count = 0;
+    if (tl.R <= 64 && grid <= kMapMax) {
+        for (int64_t b = 0; b < grid; ++b) {
+            int g, r, half, xslot;
+            mt_decode(tl, b, g, r, half, xslot);
+            m.e[b] = (uint16_t)(g | (r << 6) | ((half + 1) << 12));
+        }
+        m.count = (int32_t)grid;
+    }
+    last = tl;
+    return m;
+}
+
 template <int PREC>
 static void launch_mutual_shape(int tpl, int waves, dim3 grid, const double* pos, const double* gm,
                                 int64_t n, const int64_t* nmaj, const MutualTail& tl,
                                 double* part, hipStream_t s)
 {
     const dim3 block((unsigned)(64 * waves));
+    const MutualMap& map = mutual_map(tl, (int64_t)grid.x);
     if (tpl == 1)
         hipLaunchKernelGGL((k_force_mutual<1, 4, PREC>), grid, block, 0, s, pos, gm, n, nmaj,
-                           tl, part);
+                           tl, map, part);
     else if (tpl == 2 && waves == 2)
         hipLaunchKernelGGL((k_force_mutual<2, 2, PREC>), grid, block, 0, s, pos, gm, n, nmaj,
-                           tl, part);
+                           tl, map, part);
     else if (tpl == 2)
         hipLaunchKernelGGL((k_force_mutual<2, 4, PREC>), grid, block, 0, s, pos, gm, n, nmaj,
-                           tl, part);
+                           tl, map, part);
     else
         hipLaunchKernelGGL((k_force_mutual<4, 4, PREC>), grid, block, 0, s, pos, gm, n, nmaj,
-                           tl, part);
+                           tl, map, part);
 }
 
 template <int PREC>

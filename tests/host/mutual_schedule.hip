@@ -3,7 +3,8 @@
 // runs once, whole or as both halves (sub-phases 0-1 and 2-3, each over all
 // its targets and sources), and every body receives each of its partial
 // slots exactly once, with every slot inside the workspace.  The force pass
-// and the transpose-Jacobian pass share this decode and these slot rules.
+// and the transpose-Jacobian pass share this decode and these slot rules; the
+// force pass's kernel-argument list of it decodes to the same.
 #include "kernels_mutual.hip"
 #include <cstdio>
 #include <vector>
@@ -18,9 +19,19 @@ static int check(int64_t n, int tpl, int waves, bool verbose)
     std::vector<int> whole((size_t)R * R, 0), halves((size_t)R * R * 2, 0);
     std::vector<unsigned char> wr((size_t)n * S, 0);
     auto mark = [&](int64_t i, int slot) { if (i < n) { if (slot < 0 || slot >= S) { printf("slot %d of %d\n", slot, S); exit(1);} wr[(size_t)i * S + slot]++; } };
+    // the kernel-argument list, where it applies, decodes to the same
+    const MutualMap& map = mutual_map(tl, grid);
+    if (map.count != 0 && (map.count != grid || R > 64 || grid > kMapMax)) { printf("n=%ld map count %d\n", (long)n, map.count); return 1; }
+    if (map.count == 0 && R <= 64 && grid <= kMapMax) { printf("n=%ld map missing\n", (long)n); return 1; }
     for (int64_t b = 0; b < grid; ++b) {
         int g, r, half, xs;
         mt_decode(tl, b, g, r, half, xs);
+        if (map.count > 0) {
+            const unsigned v = map.e[b];
+            const int mg = (int)(v & 63u), mr = (int)((v >> 6) & 63u), mh = (int)(v >> 12) - 1;
+            const int mx = mh >= 0 ? R + (mr - mg) - 1 : 0;
+            if (mg != g || mr != r || mh != half || (half >= 0 && mx != xs)) { printf("n=%ld b=%ld map differs\n", (long)n, (long)b); return 1; }
+        }
         if (g < 0 || r < g || r >= R) { printf("n=%ld b=%ld bad (%d,%d)\n", (long)n, (long)b, g, r); return 1; }
         if (half < 0) {
             whole[(size_t)g * R + r]++;
