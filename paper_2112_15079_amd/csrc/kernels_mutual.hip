@@ -574,6 +574,21 @@ struct MutualMap {
     uint16_t e[kMapMax];
 };
 
+// Workgroup bid's pair from the list when it holds one, else by the closed form.
+__device__ __forceinline__ void mt_lookup(const MutualMap& map, const MutualTail& tl, int64_t bid,
+                                          int& g, int& r, int& half, int& xslot)
+{
+    if (map.count > 0) {
+        const uint32_t v = __builtin_amdgcn_readfirstlane((uint32_t)map.e[bid]);
+        g = (int)(v & 63u);
+        r = (int)((v >> 6) & 63u);
+        half = (int)(v >> 12) - 1;
+        xslot = half >= 0 ? tl.R + (r - g) - 1 : 0;
+    } else {
+        mt_decode(tl, bid, g, r, half, xslot);
+    }
+}
+
 // Half `half` of the split pair (g, r), r > g, by sub-phases: the four
 // target blocks of range g (four per lane) against source block 4r + w in
 // wave w, over sub-phases Q0 .. Q1 - 1 (half 0: 0 and 1, half 1: 2 and 3),
@@ -932,15 +947,7 @@ __global__ __launch_bounds__(64 * KMW) void k_force_mutual(const double* __restr
                                                            double* __restrict__ part)
 {
     int g, r, half, xslot;
-    if (map.count > 0) {
-        const uint32_t v = __builtin_amdgcn_readfirstlane((uint32_t)map.e[blockIdx.x]);
-        g = (int)(v & 63u);
-        r = (int)((v >> 6) & 63u);
-        half = (int)(v >> 12) - 1;
-        xslot = half >= 0 ? tl.R + (r - g) - 1 : 0;
-    } else {
-        mt_decode(tl, blockIdx.x, g, r, half, xslot);
-    }
+    mt_lookup(map, tl, blockIdx.x, g, r, half, xslot);
     mutual_unit<KMT, KMW, PREC>(pos, gm, n, n, PREC != 0 ? nmaj[0] : 0, g, r, part, tl, half,
                                 xslot);
 }

@@ -15,12 +15,12 @@ namespace {
 template <int KMT, int KMW>
 __global__ __launch_bounds__(64 * KMW) void k_force_mutual_clocked(
     const double* __restrict__ pos, const double* __restrict__ gm, int64_t n, MutualTail tl,
-    double* __restrict__ part, unsigned long long* __restrict__ clk)
+    MutualMap map, double* __restrict__ part, unsigned long long* __restrict__ clk)
 {
     const unsigned long long c0 = __builtin_amdgcn_s_memtime();
     const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
     int g, r, half, xslot;
-    mt_decode(tl, blockIdx.x, g, r, half, xslot);
+    mt_lookup(map, tl, blockIdx.x, g, r, half, xslot);
     mutual_unit<KMT, KMW, 0>(pos, gm, n, n, 0, g, r, part, tl, half, xslot);
     const unsigned long long c1 = __builtin_amdgcn_s_memtime();
     const unsigned long long t1 = __builtin_amdgcn_s_memrealtime();
@@ -68,7 +68,7 @@ extern "C" __attribute__((visibility("default"))) int clock_probe_force(const do
         if (hipEventRecord(e0, nullptr) != hipSuccess) { rc = 3; break; }
         for (int k = 0; k < per_batch; ++k)
             hipLaunchKernelGGL((k_force_mutual_clocked<4, 4>), dim3(grid), dim3(256), 0, nullptr,
-                               pos, gm, n, tl, part, clk);
+                               pos, gm, n, tl, mutual_map(tl, grid), part, clk);
         if (hipGetLastError() != hipSuccess || hipEventRecord(e1, nullptr) != hipSuccess ||
             hipEventSynchronize(e1) != hipSuccess) { rc = 4; break; }
         float ms = 0.f;

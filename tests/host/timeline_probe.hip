@@ -25,11 +25,11 @@ namespace {
 
 __global__ __launch_bounds__(256) void k_force_mutual_timeline(
     const double* __restrict__ pos, const double* __restrict__ gm, int64_t n, MutualTail tl,
-    double* __restrict__ part)
+    MutualMap map, double* __restrict__ part)
 {
     NB_MUTUAL_MARK(0);
     int g, r, half, xslot;
-    mt_decode(tl, blockIdx.x, g, r, half, xslot);
+    mt_lookup(map, tl, blockIdx.x, g, r, half, xslot);
     mutual_unit<4, 4, 0>(pos, gm, n, n, 0, g, r, part, tl, half, xslot);
     NB_MUTUAL_MARK(3);
     unsigned long long* o = g_timeline;
@@ -81,13 +81,13 @@ extern "C" __attribute__((visibility("default"))) int timeline_probe_force(
         goto done;
     for (int k = 0; k < warm; ++k)
         hipLaunchKernelGGL(k_force_mutual_timeline, dim3((unsigned)grid), dim3(256), 0, nullptr,
-                           pos, gm, n, tl, part);
+                           pos, gm, n, tl, mutual_map(tl, grid), part);
     if (hipDeviceSynchronize() != hipSuccess ||
         hipMemcpyToSymbol(HIP_SYMBOL(g_timeline), &rec, sizeof(rec)) != hipSuccess ||
         hipEventRecord(e0, nullptr) != hipSuccess)
         goto done;
     hipLaunchKernelGGL(k_force_mutual_timeline, dim3((unsigned)grid), dim3(256), 0, nullptr, pos,
-                       gm, n, tl, part);
+                       gm, n, tl, mutual_map(tl, grid), part);
     if (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
         hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
         hipMemcpy(out, rec, rec_bytes, hipMemcpyDeviceToHost) != hipSuccess ||
